@@ -1,0 +1,184 @@
+/*
+ * hybfs -- hybrid (direction-optimising) breadth-first search on one MI355X.
+ *
+ * C ABI of libhybfs.so.  Plain pointers and sizes only.  Every call returns
+ * BFS_OK (0) or a negative BFS_E_* code; on error the outputs are unspecified
+ * and bfs_last_error() holds a message for the calling thread.  Nothing aborts
+ * the process and no C++ exception crosses this boundary.
+ *
+ * The method (paper Sections 4-5): a layer-synchronous BFS in which each layer
+ * is processed either top-down (Algorithm 1: the frontier's adjacency lists
+ * are expanded into the output queue) or bottom-up (Algorithm 2: every
+ * unvisited vertex scans its adjacency list for a frontier vertex and stops at
+ * the first one; Algorithms 4-5 try the first MAX_POS positions of many
+ * vertices at once before a plain scan).  An online rule on the frontier size
+ * and edge counts (Algorithm 3, Table 2) picks the direction of each layer.
+ *
+ * Result convention (for every entry point):
+ *   level[v]  = hop distance from the root, -1 if v is not reachable;
+ *   parent[v] = the smallest-id neighbour of v one layer closer to the root,
+ *               parent[root] = root, -1 if v is not reachable.
+ * Fixing the tree this way removes the run-to-run freedom a parallel BFS has
+ * (Section 7.1), so the output does not depend on the direction schedule,
+ * the tuning parameters, batching or concurrency.
+ *
+ * Graph requirements: n in [1, 2^31-1]; row_offsets[0] = 0, non-decreasing,
+ * row_offsets[n] = nnz; col_indices in [0, n).  The graph must be undirected
+ * (both directions stored), because the bottom-up step finds a vertex's
+ * parents among its own neighbours (Section 4).  Each row must be sorted
+ * ascending unless BFS_GRAPH_SORT_ROWS is given.  Self-loops and duplicate
+ * entries are allowed and do not change the result.
+ */
+#ifndef HYBFS_H
+#define HYBFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define BFS_OK           0
+#define BFS_E_INVALID   (-1)  /* bad argument or malformed graph */
+#define BFS_E_NOMEM     (-2)  /* device or host allocation failed / over budget */
+#define BFS_E_DEVICE    (-3)  /* HIP runtime error or device-side failure */
+#define BFS_E_BUSY      (-4)  /* queue full (serving) */
+#define BFS_E_NOTFOUND  (-5)  /* unknown graph id or ticket */
+#define BFS_E_TIMEOUT   (-6)  /* a wait timed out */
+
+typedef struct bfs_graph *bfs_graph_t;
+
+/* ---- graph creation flags ---- */
+#define BFS_GRAPH_DEVICE_INPUT   1u  /* row_offsets / col_indices are device pointers */
+#define BFS_GRAPH_ASSUME_VALID   2u  /* skip the host-side structural checks */
+#define BFS_GRAPH_CHECK_SYMMETRY 4u  /* also verify that every edge is stored both ways */
+#define BFS_GRAPH_SORT_ROWS      8u  /* rows may be unsorted: sort the library's copy */
+
+/*
+ * Make a graph resident on the current HIP device.
+ *   n, nnz       vertex count and number of stored (directed) CSR entries.
+ *   row_offsets  int64[n+1]; col_indices int32[nnz]; host pointers unless
+ *                BFS_GRAPH_DEVICE_INPUT.  The library copies both; the caller
+ *                keeps ownership and may free them after the call returns.
+ *   flags        BFS_GRAPH_* bits.
+ *   out          receives the handle (immutable; safe to share across threads).
+ * Besides the copy, the library precomputes per-vertex data used by every
+ * traversal (the isolated-vertex bitmap and the degree sum).
+ * Errors: BFS_E_INVALID (n or nnz out of range, offsets not monotone or not
+ * ending at nnz, a column out of range, an unsorted row without
+ * BFS_GRAPH_SORT_ROWS, asymmetry when checked), BFS_E_NOMEM, BFS_E_DEVICE.
+ */
+int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets,
+                     const int32_t *col_indices, uint32_t flags, bfs_graph_t *out);
+
+/* Free the device copy and all workspaces.  The caller must ensure no
+ * traversal on this graph is still running. */
+int bfs_graph_destroy(bfs_graph_t g);
+
+typedef struct bfs_graph_info {
+    int64_t n;
+    int64_t nnz;
+    int64_t isolated;        /* vertices of degree 0 */
+    int64_t max_degree;
+    int64_t device_bytes;    /* graph-resident bytes (CSR + per-vertex data) */
+    int64_t workspace_bytes; /* device bytes of one single-root workspace */
+    int32_t grid_blocks;     /* default blocks of a layer kernel */
+    int32_t block_threads;   /* threads per block of a layer kernel */
+    int64_t hub_chunks;      /* top-down work items of vertices above the hub degree */
+    int32_t hub_degree;      /* degree above which a vertex's edges are split over the grid */
+    int32_t typical_layers;  /* layers the adaptive launch currently enqueues */
+} bfs_graph_info;
+
+int bfs_graph_info_get(bfs_graph_t g, bfs_graph_info *info);
+
+/* ---- direction rules (Algorithm 3, switch functions f and g) ----
+ * BFS_RULE_EDGES : top-down -> bottom-up when m_f * alpha > m_u; bottom-up ->
+ *                  top-down when n_f * beta < n (frontier vertices n_f,
+ *                  frontier edges m_f, edges of unvisited vertices m_u).
+ * BFS_RULE_TABLE : the reading that reproduces Table 2: f = floor(v_u/1024),
+ *                  g = floor(n/64), with v_u the unvisited vertex count;
+ *                  top-down -> bottom-up when n_f > f, back when n_f < g.
+ * BFS_RULE_TOPDOWN / BFS_RULE_BOTTOMUP force one direction on every layer.
+ * Either rule starts top-down and is evaluated before every layer. */
+#define BFS_RULE_EDGES     0
+#define BFS_RULE_TABLE     1
+#define BFS_RULE_TOPDOWN   2
+#define BFS_RULE_BOTTOMUP  3
+
+typedef struct bfs_options {
+    int32_t rule;              /* BFS_RULE_* */
+    int32_t alpha;             /* edge rule parameter, > 0 */
+    int32_t beta;              /* edge rule parameter, > 0 */
+    int32_t probe_k;           /* bottom-up positions tried per vertex before the
+                                  wavefront-cooperative scan (MAX_POS of Section
+                                  5.2), 0..64 */
+    int32_t small_degree;      /* top-down: vertices up to this degree get one
+                                  lane each, larger ones a whole wavefront, 1..4096 */
+    int32_t grid_blocks;       /* blocks of each layer kernel; 0 = library default */
+    int32_t words_per_wave;    /* bitmap words (64 vertices each) one wavefront
+                                  task covers: 1, 2, 4, .., 64; 0 = sized from n */
+    int32_t layers_per_launch; /* layer kernels enqueued before the single-block
+                                  finisher; 0 = adaptive per graph */
+    int32_t out_on_device;     /* 1: level_out / parent_out are device pointers */
+    int32_t async;             /* 1: return once enqueued (device outputs only, no
+                                  stats); errors surface in bfs_graph_sync */
+    int32_t reserved[2];       /* must be zero */
+    void   *stream;            /* hipStream_t to run on; NULL = default stream */
+} bfs_options;
+
+/* Fill defaults: edge rule, alpha 14, beta 24, probe_k 8, small_degree 32,
+ * automatic grid / words_per_wave / layers_per_launch, host outputs,
+ * synchronous, NULL stream. */
+void bfs_options_init(bfs_options *opt);
+
+/* One processed layer d (frontier F_d = vertices at level d). */
+typedef struct bfs_layer_stat {
+    int32_t direction;  /* 0 top-down, 1 bottom-up */
+    int32_t reserved;
+    int64_t n_f;        /* |F_d| */
+    int64_t m_f;        /* sum of degrees over F_d */
+    int64_t m_u;        /* sum of degrees over vertices not in layers 0..d */
+    int64_t v_u;        /* number of vertices not in layers 0..d */
+    double  t_us;       /* device time spent on this layer */
+} bfs_layer_stat;
+
+typedef struct bfs_stats {
+    int32_t capacity;        /* in: entries available in `layers` (may be 0) */
+    int32_t num_layers;      /* out: layers processed (deepest level + 1) */
+    bfs_layer_stat *layers;  /* in: caller-owned array of `capacity`, or NULL */
+    int64_t reached;         /* out: vertices with level >= 0 */
+    int64_t reached_degree_sum; /* out: stored entries of reached vertices;
+                                   half of it is the TEPS numerator (Section 6.3) */
+    double  device_us;       /* out: device time of the traversal launch */
+} bfs_stats;
+
+/*
+ * Single-root hybrid BFS (Algorithm 3 over Algorithms 1 and 2).
+ *   root                  vertex id in [0, n).
+ *   level_out, parent_out int32[n] each, caller-owned; device pointers if
+ *                         opt->out_on_device, else host pointers.
+ *   opt                   may be NULL (defaults).
+ *   stats                 may be NULL.  Not allowed with opt->async.
+ * Enqueued on opt->stream as one init kernel, one kernel per layer (each
+ * decides its direction on the device from the frontier counters), and a
+ * single-block finisher for layers beyond the enqueued ones.  Concurrent
+ * calls on different streams are allowed (each stream gets its own
+ * workspace); calls on one stream are ordered by the stream.
+ * Errors: BFS_E_INVALID, BFS_E_NOMEM, BFS_E_DEVICE.
+ */
+int bfs_run(bfs_graph_t g, int32_t root, int32_t *level_out, int32_t *parent_out,
+            const bfs_options *opt, bfs_stats *stats);
+
+/* Wait for all work enqueued on `stream` for this graph and report any
+ * failure of asynchronous runs (BFS_E_DEVICE). */
+int bfs_graph_sync(bfs_graph_t g, void *stream);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *bfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYBFS_H */

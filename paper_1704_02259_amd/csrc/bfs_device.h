@@ -1,0 +1,101 @@
+// Shared layout between the host runtime and the gfx950 kernels of libhybfs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hybfs {
+
+constexpr int kBlock = 256;                    // threads per block of the layer kernels
+constexpr int kWave = 64;                      // CDNA wavefront
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kFinishBlock = 1024;             // single-block finisher
+constexpr int kSlots = 4;                      // ring of per-layer counter slots
+
+enum { DIR_TD = 0, DIR_BU = 1 };
+enum { RULE_EDGES = 0, RULE_TABLE = 1, RULE_TOPDOWN = 2, RULE_BOTTOMUP = 3 };
+
+// Counters of one frontier F_d, accumulated while F_{d-1} is processed.
+struct Slot {
+    unsigned long long n_f;          // |F_d|
+    unsigned long long m_f;          // sum of deg over F_d
+    unsigned long long pad[6];
+};
+
+// What the kernel of layer d needs from the layers before it.  Two copies
+// alternate: the kernel of layer d reads st[d & 1] and its block 0 writes
+// st[(d + 1) & 1], which no block of the same kernel reads.
+struct LayerState {
+    int d;                           // layer index
+    int dir_prev;                    // direction of layer d-1 (top-down before layer 0)
+    long long m_u;                   // edges of vertices not in layers 0..d-1
+    long long v_u;                   // vertices not in layers 0..d-1
+    long long reached;               // vertices in layers 0..d-1
+    long long reached_deg;           // their degree sum
+    long long pad[3];
+};
+
+// Trace of one processed layer, written by block 0.
+struct LayerRec {
+    int dir;
+    int pad;
+    long long n_f, m_f, m_u, v_u;
+    unsigned long long t;            // device wall clock when the layer started
+};
+
+struct Ctrl {
+    int done;                        // set once a layer finds an empty frontier
+    int nlayers;
+    int parity;                      // which LayerState the next layer reads
+    int root;
+    long long reached;
+    long long reached_deg;
+    unsigned long long t_end;
+    int *level;                      // outputs of the current traversal
+    int *parent;
+    long long pad1;
+    LayerState st[2];
+    Slot slot[kSlots];
+};
+
+// A block of 2^hub_log2 consecutive edges of a high-degree vertex.
+struct Item {
+    int u;
+    int chunk;
+};
+
+struct Params {
+    long long n, nnz, W;                 // vertices, stored entries, bitmap words
+    const long long *off;                // int64 [n+1]
+    const int *col;                      // int32 [nnz], rows ascending
+    const unsigned long long *iso;       // [W] bit set: degree 0 or v >= n
+    const Item *hub;                     // chunks of every vertex with degree > hub_deg
+    long long n_hub;
+    int hub_log2;
+    int hub_deg;
+    int small_deg;                       // top-down: one lane per vertex up to this degree
+    int probe_k;                         // bottom-up positions tried per lane
+    int wpg;                             // bitmap words per wavefront task (1..64)
+    unsigned long long *vis;             // [W] finished layers (+ iso bits)
+    unsigned long long *bm;              // [3W] rotating frontier / next / spare
+    int *level, *parent;                 // outputs [n]
+    Ctrl *ctrl;
+    LayerRec *trace;
+    int trace_cap;
+    int root;
+    int rule;
+    long long alpha, beta;
+};
+
+// Launchers (defined in bfs_kernels.hip).
+hipError_t launch_init(const Params &p, int grid, hipStream_t s);
+hipError_t launch_layer(const Params &p, int parity, int grid, hipStream_t s);
+hipError_t launch_finish(const Params &p, hipStream_t s);
+hipError_t launch_iso_template(const long long *off, long long n, long long W,
+                               unsigned long long *iso, hipStream_t s);
+void *kernel_ptr_init();
+void *kernel_ptr_layer();
+void *kernel_ptr_finish();
+int layer_blocks_per_cu();
+
+}  // namespace hybfs

