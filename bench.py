@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the single-root hybrid BFS on one MI355X.
+
+A step is one traversal from each of the workload's roots (64 seeded roots of
+degree > 0 on a seeded Kronecker graph, SCALE 20 and edgefactor 16 by
+default), each a full hybrid BFS writing level and canonical parent arrays
+into device buffers.  The graph is resident in HBM before timing starts.
+
+value = harmonic mean over roots of TE_i / t_i (Graph500 TEPS, Section 6.3),
+with TE_i the undirected edges in root i's component and t_i the HIP-event
+time of its traversal on the stream, median over the timed steps.
+
+Prints one JSON line.  Also reports the layer kernel's achieved algorithmic
+bandwidth against the MI355X HBM peak and the serial CPU oracle's rate on a
+bounded sample of the same roots.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "harmonic-mean GTEPS"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("bfs_kernels.hip", "bfs_device.h"):
+        with open(os.path.join(ROOT, "paper_1704_02259_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per layer-kernel launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_bfs_layer_kernel_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="kron20", help="kron<S> (edgefactor 16) or er20")
+    ap.add_argument("--roots", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=16, help="roots timed on the CPU oracle")
+    ap.add_argument("--balg-roots", type=int, default=64, help="roots whose algorithmic bytes are counted")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
+    ap.add_argument("--alpha", type=int, default=0)
+    ap.add_argument("--beta", type=int, default=0)
+    ap.add_argument("--probe-k", type=int, default=-1)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import inputs
+    from paper_1704_02259_amd import _build, hybfs
+    if not os.path.exists(_build.LIB) or not os.path.exists(inputs._LIB):
+        import __graft_entry__
+        __graft_entry__.build()
+    hybfs.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    g = inputs.workload_graph(args.workload)
+    roots = inputs.workload_roots(args.workload, g, args.roots)
+    log(f"graph {args.workload}: n={g.n} nnz={g.nnz} gen {time.time() - t0:.1f}s, {len(roots)} roots")
+
+    t0 = time.time()
+    G = hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID)
+    info = G.info()
+    log(f"resident in {time.time() - t0:.1f}s; grid {info.grid_blocks}x{info.block_threads}, "
+        f"slab_k {info.slab_k}, hub degree {info.hub_degree}, hub chunks {info.hub_chunks}")
+
+    kw = {}
+    if args.alpha:
+        kw["alpha"] = args.alpha
+    if args.beta:
+        kw["beta"] = args.beta
+    if args.probe_k >= 0:
+        kw["probe_k"] = args.probe_k
+
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    lv = torch.empty(g.n, dtype=torch.int32, device=dev)
+    pa = torch.empty(g.n, dtype=torch.int32, device=dev)
+
+    # one synchronous run per root first: adapts the launch depth, gives traces
+    traces = []
+    for r in roots:
+        _, _, st = G.run(int(r), lv, pa, stream=sp, stats=True, **kw)
+        traces.append(st)
+    log("layers per root:", sorted({st["num_layers"] for st in traces}))
+
+    def one_step(evs=None):
+        for i, r in enumerate(roots):
+            if evs is not None:
+                evs[i][0].record(stream)
+            G.run(int(r), lv, pa, stream=sp, async_=1, **kw)
+            if evs is not None:
+                evs[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in roots] for _ in range(K)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(K):
+        one_step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    hybfs.bfs_graph_sync(G.handle, sp)
+    per_root_ms = np.median(np.array([[a.elapsed_time(b) for a, b in evs[k]] for k in range(K)]), axis=0)
+    ms_per_step = wall * 1000.0 / K
+
+    # layer-kernel durations with HIP events around every launch (separate pass)
+    prof = []
+    for r in roots:
+        _, _, st = G.run(int(r), lv, pa, stream=sp, stats=True, profile_layers=1, **kw)
+        prof.append(st)
+    layer_launches = sum(st["layer_launches"] for st in prof)
+    layer_us = sum(st["layer_kernel_us"] for st in prof)
+
+    # ---- oracle legs (CPU) ----
+    import oracle
+    cpu = None
+    parity_ok = None
+    # without the oracle legs (profiling runs) the library's own count stands in
+    te = np.array([st["reached_degree_sum"] / 2.0 for st in traces])
+    balg_layers = None
+    if not args.no_cpu:
+        # serial oracle timed on a bounded sample of the same roots, 1 thread
+        ns = min(args.cpu_sample, len(roots))
+        cpu_t, cpu_te, levels = [], [], {}
+        parity_ok = True
+        for r in roots[:ns]:
+            t0 = time.perf_counter()
+            elv, epa = oracle.bfs(g, int(r))
+            cpu_t.append(time.perf_counter() - t0)
+            cpu_te.append(oracle.traversed_edges(g, elv))
+            G.run(int(r), lv, pa, stream=sp)
+            stream.synchronize()
+            parity_ok &= bool(np.array_equal(lv.cpu().numpy(), elv) and np.array_equal(pa.cpu().numpy(), epa))
+        cpu_rates = np.array(cpu_te) / np.array(cpu_t) / 1e9
+        cpu = {"value": float(len(cpu_rates) / np.sum(1.0 / cpu_rates)), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle",
+               "sample": f"first {ns} of the {len(roots)} roots, serial C oracle (FIFO BFS levels + "
+                         f"canonical-parent pass, gcc -O2), one thread; {sum(cpu_t):.1f}s of CPU work"}
+        log(f"cpu oracle: {cpu['value']:.4f} GTEPS over {ns} roots; parity on sample: {parity_ok}")
+
+        # exact TE and algorithmic bytes per root from the oracle (not timed)
+        nb = min(args.balg_roots, len(roots))
+
+        def work(r):
+            elv, _ = oracle.bfs(g, int(r))
+            te_r = oracle.traversed_edges(g, elv)
+            res = oracle.algorithmic_bytes(g, elv) if nb else None
+            return te_r, res
+
+        with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            outs = list(ex.map(work, [int(r) for r in roots]))
+        te = np.array([o[0] for o in outs])
+        balg_layers = [sum(min(td, bu) for td, bu in o[1]["per_layer"]) for o in outs[:nb]]
+        balg_total = [o[1]["bytes"] for o in outs[:nb]]
+
+    gteps = te / (per_root_ms * 1e-3) / 1e9
+    hm = float(len(gteps) / np.sum(1.0 / gteps))
+    agg = float(te.sum() / (ms_per_step * 1e-3) / 1e9)
+
+    roofline = None
+    if balg_layers is not None:
+        nb = len(balg_layers)
+        launches_b = sum(prof[i]["layer_launches"] for i in range(nb))
+        us_b = sum(prof[i]["layer_kernel_us"] for i in range(nb))
+        bytes_per_launch = sum(balg_layers) / launches_b
+        avg_us = us_b / launches_b
+        achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+        traversal_us = sum(per_root_ms[:nb]) * 1e3
+        traffic = measured_traffic(args.workload)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                    "kernel": "bfs_layer_kernel", "launches": launches_b,
+                    "alg_bytes_per_launch": round(bytes_per_launch, 1), "avg_launch_us": round(avg_us, 3),
+                    "traversal_frac": round(sum(balg_total) / (traversal_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}
+
+    s = int(args.workload[4:]) if args.workload.startswith("kron") else None
+    out = {
+        "metric": METRIC,
+        "value": round(hm, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": (f"kronecker_scale{s}_ef16_{len(roots)}roots_single_root_hybrid_bfs"
+                                if s is not None else f"{args.workload}_{len(roots)}roots"),
+                   "n": g.n, "nnz": g.nnz, "roots": len(roots),
+                   "graph_seed": inputs.GRAPH_SEED.get(s) if s is not None else inputs.ER20_SEED},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "gteps_aggregate": round(agg, 3),
+        "median_root_us": round(float(np.median(per_root_ms)) * 1e3, 2),
+        "min_root_gteps": round(float(gteps.min()), 3),
+        "parity_sample_ok": parity_ok,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,7 +64,9 @@ typedef struct bfs_graph *bfs_graph_t;
  *   flags        BFS_GRAPH_* bits.
  *   out          receives the handle (immutable; safe to share across threads).
  * Besides the copy, the library precomputes per-vertex data used by every
- * traversal (the isolated-vertex bitmap and the degree sum).
+ * traversal: the degree array, the isolated-vertex bitmap, and a
+ * position-major copy of the first entries of every row (the vector-friendly
+ * layout of Section 5's bottom-up probes).
  * Errors: BFS_E_INVALID (n or nnz out of range, offsets not monotone or not
  * ending at nnz, a column out of range, an unsorted row without
  * BFS_GRAPH_SORT_ROWS, asymmetry when checked), BFS_E_NOMEM, BFS_E_DEVICE.
@@ -85,9 +87,13 @@ typedef struct bfs_graph_info {
     int64_t workspace_bytes; /* device bytes of one single-root workspace */
     int32_t grid_blocks;     /* default blocks of a layer kernel */
     int32_t block_threads;   /* threads per block of a layer kernel */
-    int64_t hub_chunks;      /* top-down work items of vertices above the hub degree */
-    int32_t hub_degree;      /* degree above which a vertex's edges are split over the grid */
+    int32_t slab_k;          /* first entries of each row kept position-major for the
+                                bottom-up probes */
+    int32_t chunk_edges;     /* top-down hub chunk size in edges */
     int32_t typical_layers;  /* layers the adaptive launch currently enqueues */
+    int32_t hub_degree;      /* top-down: vertices above this degree are expanded
+                                through a grid-wide table of edge chunks */
+    int64_t hub_chunks;      /* entries of that table */
 } bfs_graph_info;
 
 int bfs_graph_info_get(bfs_graph_t g, bfs_graph_info *info);
@@ -113,8 +119,9 @@ typedef struct bfs_options {
     int32_t probe_k;           /* bottom-up positions tried per vertex before the
                                   wavefront-cooperative scan (MAX_POS of Section
                                   5.2), 0..64 */
-    int32_t small_degree;      /* top-down: vertices up to this degree get one
-                                  lane each, larger ones a whole wavefront, 1..4096 */
+    int32_t small_degree;      /* reserved for the top-down degree split, 1..4096
+                                  (the kernels balance each bitmap word's edges
+                                  over the lanes and do not use it) */
     int32_t grid_blocks;       /* blocks of each layer kernel; 0 = library default */
     int32_t words_per_wave;    /* bitmap words (64 vertices each) one wavefront
                                   task covers: 1, 2, 4, .., 64; 0 = sized from n */
@@ -123,7 +130,14 @@ typedef struct bfs_options {
     int32_t out_on_device;     /* 1: level_out / parent_out are device pointers */
     int32_t async;             /* 1: return once enqueued (device outputs only, no
                                   stats); errors surface in bfs_graph_sync */
-    int32_t reserved[2];       /* must be zero */
+    int32_t profile_layers;    /* 1: bracket every layer kernel with HIP events on
+                                  the stream and report their durations in stats
+                                  (synchronous runs with stats only) */
+    int32_t graph_launch;      /* 1: replay a hipGraph of the launch sequence,
+                                  captured once per workspace and option set, with
+                                  only the root and the output pointers updated per
+                                  run; 0 (default): enqueue the kernels one by one
+                                  (measured faster on MI355X for this sequence) */
     void   *stream;            /* hipStream_t to run on; NULL = default stream */
 } bfs_options;
 
@@ -140,7 +154,10 @@ typedef struct bfs_layer_stat {
     int64_t m_f;        /* sum of degrees over F_d */
     int64_t m_u;        /* sum of degrees over vertices not in layers 0..d */
     int64_t v_u;        /* number of vertices not in layers 0..d */
-    double  t_us;       /* device time spent on this layer */
+    double  t_us;       /* time of this layer (HIP events, profile_layers runs
+                           only, else 0); layers past the enqueued kernels,
+                           run by the finisher, report 0 */
+    double  kernel_us;  /* HIP-event duration of this layer's kernel (profile_layers), else 0 */
 } bfs_layer_stat;
 
 typedef struct bfs_stats {
@@ -150,7 +167,12 @@ typedef struct bfs_stats {
     int64_t reached;         /* out: vertices with level >= 0 */
     int64_t reached_degree_sum; /* out: stored entries of reached vertices;
                                    half of it is the TEPS numerator (Section 6.3) */
-    double  device_us;       /* out: device time of the traversal launch */
+    double  device_us;       /* out: HIP-event time of the whole traversal */
+    int32_t layer_launches;  /* out: layer kernels enqueued (some may find the
+                                traversal already finished) */
+    int32_t reserved;
+    double  layer_kernel_us; /* out: sum of the HIP-event durations of all layer
+                                kernels (profile_layers), else 0 */
 } bfs_stats;
 
 /*

@@ -15,7 +15,7 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # packed fp32 instructions stay disabled in every HIP build of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-Wno-unused-value",
 ]
 
 

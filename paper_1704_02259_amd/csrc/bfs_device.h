@@ -15,11 +15,12 @@ constexpr int kSlots = 4;                      // ring of per-layer counter slot
 enum { DIR_TD = 0, DIR_BU = 1 };
 enum { RULE_EDGES = 0, RULE_TABLE = 1, RULE_TOPDOWN = 2, RULE_BOTTOMUP = 3 };
 
-// Counters of one frontier F_d, accumulated while F_{d-1} is processed.
+// Counters of one frontier F_d, accumulated while F_{d-1} is processed.  Each
+// block adds into sub-counter blockIdx % kSub, one 64-byte line apart, so the
+// atomics of a layer spread over kSub addresses; readers sum the sub-counters.
+constexpr int kSub = 16;
 struct Slot {
-    unsigned long long n_f;          // |F_d|
-    unsigned long long m_f;          // sum of deg over F_d
-    unsigned long long pad[6];
+    unsigned long long c[kSub][8];   // c[k][0]: part of |F_d|, c[k][1]: part of sum deg(F_d)
 };
 
 // What the kernel of layer d needs from the layers before it.  Two copies
@@ -53,12 +54,13 @@ struct Ctrl {
     unsigned long long t_end;
     int *level;                      // outputs of the current traversal
     int *parent;
-    long long pad1;
+    int status;                      // nonzero: a device-side consistency check failed
+    int pad1;
     LayerState st[2];
     Slot slot[kSlots];
 };
 
-// A block of 2^hub_log2 consecutive edges of a high-degree vertex.
+// A top-down work item: the `chunk`-th block of 2^chunk_log2 edges of u.
 struct Item {
     int u;
     int chunk;
@@ -69,13 +71,19 @@ struct Params {
     const long long *off;                // int64 [n+1]
     const int *col;                      // int32 [nnz], rows ascending
     const unsigned long long *iso;       // [W] bit set: degree 0 or v >= n
-    const Item *hub;                     // chunks of every vertex with degree > hub_deg
+    const int *deg;                      // int32 [n] row lengths
+    const int *slab;                     // int32 [slab_k * n] position-major first
+                                         // neighbours: slab[p*n + v] = p-th entry of
+                                         // row v, or -1 past its end
+    int slab_k;
+    int chunk_log2;                      // top-down hub chunks cover 2^chunk_log2 edges
+    const Item *hub;                     // every chunk of every vertex of degree > hub_deg
     long long n_hub;
-    int hub_log2;
     int hub_deg;
-    int small_deg;                       // top-down: one lane per vertex up to this degree
+    int small_deg;                       // unused by the kernels (kept for layout)
     int probe_k;                         // bottom-up positions tried per lane
-    int wpg;                             // bitmap words per wavefront task (1..64)
+    int wpg;                             // bottom-up: bitmap words per wavefront task (1..64)
+    int wpg_td;                          // top-down: bitmap words per wavefront task (1..64)
     unsigned long long *vis;             // [W] finished layers (+ iso bits)
     unsigned long long *bm;              // [3W] rotating frontier / next / spare
     int *level, *parent;                 // outputs [n]
@@ -85,11 +93,13 @@ struct Params {
     int root;
     int rule;
     long long alpha, beta;
+    int timing;                          // record device timestamps per layer
+    int pad1;
 };
 
 // Launchers (defined in bfs_kernels.hip).
 hipError_t launch_init(const Params &p, int grid, hipStream_t s);
-hipError_t launch_layer(const Params &p, int parity, int grid, hipStream_t s);
+hipError_t launch_layer(const Params &p, int layer, int grid, hipStream_t s);
 hipError_t launch_finish(const Params &p, hipStream_t s);
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);

@@ -51,6 +51,30 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
+// Inclusive prefix sum across the wavefront.
+__device__ __forceinline__ long long wave_incl_scan(long long x)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, (unsigned)o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Inclusive prefix sum of 32-bit values across the wavefront.
+__device__ __forceinline__ int wave_incl_scan32(int x)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, (unsigned)o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
 __device__ __forceinline__ bool test_bit(const unsigned long long *bm, int v)
 {
     return (bm[v >> 6] >> (v & 63)) & 1ull;
@@ -77,100 +101,274 @@ __device__ __forceinline__ int decide(const Params &P, int cur, long long n_f, l
 }
 
 // ---------------------------------------------------------------------------
-// One frontier edge u -> v of a top-down layer.  v is a candidate when it is
-// in no layer <= d (neither in vis nor in the frontier).  A plain read of
-// parent[v] skips the atomic when a smaller frontier neighbour already won;
-// the edge that replaces the initial -1 discovers v.
-__device__ __forceinline__ void td_edge(const Params &P, int d, int u, int v,
-                                        const unsigned long long *front, unsigned long long *next,
-                                        unsigned long long &nf, unsigned long long &mf)
+// Up to four frontier edges (u_q -> col[j_q]) per lane of a top-down layer.
+// A target v is a candidate when it is in no layer <= d (neither in vis nor
+// in the frontier).  Canonical parent = the minimum frontier neighbour: a plain
+// read of parent[v] skips the atomic when a smaller neighbour already won, and
+// the edge whose unsigned atomicMin replaces the initial -1 discovers v.  The
+// loads of the four edges are issued together to overlap their latency.
+__device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq)[4],
+                                          const long long (&jq)[4], const bool (&okq)[4],
+                                          const unsigned long long *front, unsigned long long *next,
+                                          unsigned long long &nf, unsigned long long &mf,
+                                          unsigned long long &nh)
 {
-    const int w = v >> 6;
-    const unsigned long long bit = 1ull << (v & 63);
-    if ((P.vis[w] | front[w]) & bit) return;
-    const unsigned p = (unsigned)P.parent[v];
-    if ((unsigned)u >= p) return;
-    const unsigned old = atomicMin((unsigned int *)&P.parent[v], (unsigned int)u);
-    if (old == 0xFFFFFFFFu) {
-        P.level[v] = d + 1;
-        atomicOr(&next[w], bit);
-        nf += 1;
-        mf += (unsigned long long)(P.off[v + 1] - P.off[v]);
+    int v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        bool ok = okq[q];
+        if (ok && (unsigned long long)jq[q] >= (unsigned long long)P.nnz) {
+            // an edge index outside the CSR would be a kernel bug: report it
+            atomicOr((unsigned *)&P.ctrl->status, 4u);
+            ok = false;
+        }
+        v[q] = ok ? P.col[jq[q]] : -1;
+    }
+    bool cand[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        cand[q] = false;
+        if (v[q] >= 0) {
+            const int w = v[q] >> 6;
+            cand[q] = !(((P.vis[w] | front[w]) >> (v[q] & 63)) & 1ull);
+        }
+    }
+    unsigned pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pv[q] = cand[q] ? (unsigned)P.parent[v[q]] : 0u;
+    unsigned old[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        cand[q] = cand[q] && (unsigned)uq[q] < pv[q];
+        old[q] = cand[q] ? atomicMin((unsigned int *)&P.parent[v[q]], (unsigned int)uq[q]) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (cand[q] && old[q] == 0xFFFFFFFFu) {
+            P.level[v[q]] = d + 1;
+            atomicOr(&next[v[q] >> 6], 1ull << (v[q] & 63));
+            nf += 1;
+            const int dv = P.deg[v[q]];
+            mf += (unsigned long long)dv;
+            nh += dv > P.hub_deg;
+        }
     }
 }
 
-// Top-down step: the frontier bitmap is scanned 64 words per wavefront
-// iteration; each nonzero word's vertices are expanded by degree class
-// (one lane per vertex up to small_deg, the whole wavefront per vertex up to
-// hub_deg).  Vertices above hub_deg are expanded through the static hub-chunk
-// table, so their edges are spread over the whole grid.
+// Position of the k-th set bit (k from 0) of a 64-bit word.
+__device__ __forceinline__ int select_bit(unsigned long long x, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int width = 32; width > 0; width >>= 1) {
+        const unsigned long long low = x & ((1ull << width) - 1ull);
+        const int c = __popcll(low);
+        if (k >= c) {
+            k -= c;
+            x >>= width;
+            pos += width;
+        } else {
+            x = low;
+        }
+    }
+    return pos;
+}
+
+// Largest lane l whose (non-decreasing across lanes) value key_l is <= x.
+__device__ __forceinline__ int lane_search(int key, int x)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int c = lo + step;
+        if (__shfl(key, c) <= x) lo = c;
+    }
+    return lo;
+}
+
+// Top-down step (Algorithm 1).
+//  * A wavefront task covers G bitmap words.  The task's frontier vertices are
+//    laid out over the lanes (64 per round, found by a prefix sum of the
+//    words' popcounts and a select of the set bit), and the edges of those
+//    vertices are laid end to end (prefix sum of their degrees) and expanded
+//    256 per round, four per lane: the work of a task is balanced over the
+//    lanes whatever the degree mix, and its dependent loads are shared.
+//  * Vertices of degree > hub_deg are expanded through the static table of
+//    their 2^chunk_log2-edge chunks, 64 table entries per wavefront step, so a
+//    hub's edges spread over the whole grid.
 __device__ void top_down_step(const Params &P, int d, const unsigned long long *front,
                               unsigned long long *next, unsigned long long &nf,
-                              unsigned long long &mf, long long gwave, long long nwaves)
+                              unsigned long long &mf, unsigned long long &nh, bool hubs_in_front,
+                              long long gwave, long long nwaves)
 {
     const int lane = __lane_id();
-    const int G = P.wpg;
+    const int G = P.wpg_td;
     for (long long base = gwave * G; base < P.W; base += nwaves * G) {
         const long long myw = base + lane;
         const unsigned long long fwl = (lane < G && myw < P.W) ? front[myw] : 0ull;
-        unsigned long long nz = __ballot(fwl != 0ull);
-        while (nz) {
-            const int i = __ffsll((long long)nz) - 1;
-            nz &= nz - 1;
-            const long long w = base + i;
-            const unsigned long long fw = bcast_u64(fwl, i);
-            if (lane == 0) P.vis[w] |= fw;       // F_d joins the finished layers
-            const bool mine = (fw >> lane) & 1ull;
-            const int u = (int)((w << 6) + lane);
-            long long s = 0, e = 0;
-            if (mine) {
-                s = P.off[u];
-                e = P.off[u + 1];
+        if (fwl) P.vis[myw] |= fwl;              // F_d joins the finished layers (lane owns word)
+        const int cnt = __popcll(fwl);
+        const int cincl = wave_incl_scan32(cnt);
+        const int cex = cincl - cnt;
+        const int V = __builtin_amdgcn_readlane(cincl, 63);
+        for (int vr = 0; vr < V; vr += 64) {
+            // cross-lane reads run with every lane active (an inactive source
+            // lane would read as 0); only lanes with vi < V use the result
+            const int vi = vr + lane;
+            const bool vok = vi < V;
+            const int l = lane_search(cex, vok ? vi : 0);
+            const unsigned long long fw = (unsigned long long)__shfl((long long)fwl, l);
+            const int kth = vi - __shfl(cex, l);
+            int u = -1, dl = 0;
+            long long sl = 0;
+            if (vok) {
+                u = (int)(((base + l) << 6) + select_bit(fw, kth));
+                if ((unsigned)u >= (unsigned)P.n) {   // would be a kernel bug: report it
+                    atomicOr((unsigned *)&P.ctrl->status, 8u);
+                    u = 0;
+                }
+                dl = P.deg[u];
+                sl = P.off[u];
+                if (dl > P.hub_deg) dl = 0;      // expanded through the hub table
             }
-            const long long deg = e - s;
-            // one lane per low-degree vertex
-            if (mine && deg <= P.small_deg) {
-                for (long long j = s; j < e; ++j) td_edge(P, d, u, P.col[j], front, next, nf, mf);
-            }
-            // the whole wavefront per medium-degree vertex
-            unsigned long long med = __ballot(mine && deg > P.small_deg && deg <= P.hub_deg);
-            while (med) {
-                const int k = __ffsll((long long)med) - 1;
-                med &= med - 1;
-                const int uk = __builtin_amdgcn_readlane(u, k);
-                const long long sk = bcast64(s, k), ek = bcast64(e, k);
-                for (long long j = sk + lane; j < ek; j += 64)
-                    td_edge(P, d, uk, P.col[j], front, next, nf, mf);
+            const int incl = wave_incl_scan32(dl);
+            const int ex = incl - dl;
+            const int E = __builtin_amdgcn_readlane(incl, 63);
+            for (int r0 = 0; r0 < E; r0 += 256) {
+                int uq[4];
+                long long jq[4];
+                bool okq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = r0 + q * 64 + lane;
+                    okq[q] = idx < E;
+                    const int lo = lane_search(ex, idx);
+                    uq[q] = __shfl(u, lo);
+                    jq[q] = __shfl(sl, lo) + (idx - __shfl(ex, lo));
+                }
+                td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh);
             }
         }
     }
-    // high-degree frontier vertices: chunks of 2^hub_log2 edges over the grid
-    for (long long c = gwave; c < P.n_hub; c += nwaves) {
-        const Item it = P.hub[c];
-        if (!test_bit(front, it.u)) continue;
-        const long long s = P.off[it.u] + ((long long)it.chunk << P.hub_log2);
-        const long long e = min(s + (1ll << P.hub_log2), P.off[it.u + 1]);
-        for (long long j = s + lane; j < e; j += 64) td_edge(P, d, it.u, P.col[j], front, next, nf, mf);
+    // high-degree frontier vertices: the hub chunk table, 64 entries per step,
+    // lane l of wavefront g taking entry g + l * nwaves so that the adjacent
+    // chunks of one hub go to different wavefronts
+    const long long CH = 1ll << P.chunk_log2;
+    const long long n_hub = hubs_in_front ? P.n_hub : 0;   // nothing to find otherwise
+    for (long long b0 = gwave; b0 < n_hub; b0 += nwaves * 64) {
+        const long long idx = b0 + (long long)lane * nwaves;
+        Item it{-1, 0};
+        if (idx < P.n_hub) it = P.hub[idx];
+        const bool hit = it.u >= 0 && test_bit(front, it.u);
+        unsigned long long m = __ballot(hit);
+        while (m) {
+            const int k = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int uh = __builtin_amdgcn_readlane(it.u, k);
+            const int ch = __builtin_amdgcn_readlane(it.chunk, k);
+            const long long s = P.off[uh] + ((long long)ch << P.chunk_log2);
+            const long long e = min(s + CH, P.off[uh + 1]);
+            for (long long r0 = s; r0 < e; r0 += 256) {
+                int uq[4];
+                long long jq[4];
+                bool okq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uq[q] = uh;
+                    jq[q] = r0 + q * 64 + lane;
+                    okq[q] = jq[q] < e;
+                }
+                td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh);
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Bottom-up step.  A wavefront loads 64 words of vis and of the frontier,
-// then handles each word that still has unvisited vertices, one lane per
-// vertex:
-//   phase 1 (Algorithms 4-5): every unvisited lane tests positions 0..K-1 of
-//            its own ascending row against the frontier bitmap, four
-//            positions per round;
+// Bottom-up step.  A wavefront task covers G bitmap words; the words that
+// still have unvisited vertices are taken two at a time, lane i handling
+// vertex i of both, so the loads of two words overlap:
+//   phase 1 (Algorithms 4-5): every unvisited lane tests the first positions
+//            of its ascending row against the frontier bitmap -- the first
+//            slab_k from the position-major slab (coalesced, issued together
+//            with the degree load), the rest up to K from the column array,
+//            four per round;
 //   phase 2 (Algorithm 2 for the lanes left over): each unresolved row is
 //            scanned by the whole wavefront, 64 entries per step, and the
 //            first hit is taken with ballot + find-first-set.
 // The first hit in ascending order is the canonical parent.
+__device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned long long *front,
+                                                 long long v, bool act, int dg, int KS, int K,
+                                                 bool &found, int &par)
+{
+    const int lane = __lane_id();
+    // phase 1b: positions KS..K-1 from the column array
+    long long s = 0;
+    const bool need_s = act && !found && dg > KS;
+    if (need_s) s = P.off[v];
+    const long long e = s + dg;
+    bool live = need_s && K > KS;
+    for (int p0 = KS; p0 < K; p0 += 4) {
+        if (!__ballot(live)) break;
+        int c0 = -1, c1 = -1, c2 = -1, c3 = -1;
+        if (live) {
+            const long long b = s + p0;
+            c0 = P.col[b];
+            if (b + 1 < e && p0 + 1 < K) c1 = P.col[b + 1];
+            if (b + 2 < e && p0 + 2 < K) c2 = P.col[b + 2];
+            if (b + 3 < e && p0 + 3 < K) c3 = P.col[b + 3];
+        }
+        bool h0 = false, h1 = false, h2 = false, h3 = false;
+        if (c0 >= 0) h0 = test_bit(front, c0);
+        if (c1 >= 0) h1 = test_bit(front, c1);
+        if (c2 >= 0) h2 = test_bit(front, c2);
+        if (c3 >= 0) h3 = test_bit(front, c3);
+        if (live) {
+            if (h0) { found = true; par = c0; }
+            else if (h1) { found = true; par = c1; }
+            else if (h2) { found = true; par = c2; }
+            else if (h3) { found = true; par = c3; }
+            if (found || s + p0 + 4 >= e) live = false;
+        }
+    }
+    // phase 2: the rest of each unresolved row, one row at a time
+    const int KP = max(K, KS);
+    unsigned long long rem = __ballot(need_s && !found && dg > KP);
+    while (rem) {
+        const int k = __ffsll((long long)rem) - 1;
+        rem &= rem - 1;
+        const long long sk = bcast64(s, k) + KP;
+        const long long ek = bcast64(e, k);
+        int hitv = -1;
+        for (long long b = sk; b < ek; b += 64) {
+            const long long j = b + lane;
+            int u = 0;
+            bool hit = false;
+            if (j < ek) {
+                u = P.col[j];
+                hit = test_bit(front, u);
+            }
+            const unsigned long long hb = __ballot(hit);
+            if (hb) {
+                hitv = __builtin_amdgcn_readlane(u, __ffsll((long long)hb) - 1);
+                break;
+            }
+        }
+        if (hitv >= 0 && lane == k) {
+            found = true;
+            par = hitv;
+        }
+    }
+}
+
 __device__ void bottom_up_step(const Params &P, int d, const unsigned long long *front,
                                unsigned long long *next, unsigned long long &nf,
-                               unsigned long long &mf, long long gwave, long long nwaves)
+                               unsigned long long &mf, unsigned long long &nh, long long gwave,
+                               long long nwaves)
 {
     const int lane = __lane_id();
     const int K = P.probe_k;
+    const int KS = min(P.slab_k, K);
     const int G = P.wpg;
     for (long long base = gwave * G; base < P.W; base += nwaves * G) {
         const long long myw = base + lane;
@@ -184,133 +382,160 @@ __device__ void bottom_up_step(const Params &P, int d, const unsigned long long 
         if (inr && (fwl & ~vwl) && ((vwl | fwl) == ~0ull)) P.vis[myw] = vwl | fwl;
         unsigned long long todo = __ballot((vwl | fwl) != ~0ull);
         while (todo) {
-            const int i = __ffsll((long long)todo) - 1;
+            int wi[2];
+            wi[0] = __ffsll((long long)todo) - 1;
             todo &= todo - 1;
-            const long long w = base + i;
-            const unsigned long long seen = bcast_u64(vwl | fwl, i);
-            const unsigned long long vw = bcast_u64(vwl, i);
-            const long long v = (w << 6) + lane;
-            const bool act = !((seen >> lane) & 1ull);
-            long long s = 0, e = 0;
-            if (act) {
-                s = P.off[v];
-                e = P.off[v + 1];
+            wi[1] = -1;
+            if (todo) {
+                wi[1] = __ffsll((long long)todo) - 1;
+                todo &= todo - 1;
             }
-            bool found = false;
-            int par = -1;
-            bool live = act && s < e;
-            for (int p0 = 0; p0 < K; p0 += 4) {
-                if (!__ballot(live)) break;
-                int c0 = -1, c1 = -1, c2 = -1, c3 = -1;
-                if (live) {
-                    const long long b = s + p0;
-                    c0 = P.col[b];
-                    if (b + 1 < e && p0 + 1 < K) c1 = P.col[b + 1];
-                    if (b + 2 < e && p0 + 2 < K) c2 = P.col[b + 2];
-                    if (b + 3 < e && p0 + 3 < K) c3 = P.col[b + 3];
-                }
-                bool h0 = false, h1 = false, h2 = false, h3 = false;
-                if (c0 >= 0) h0 = test_bit(front, c0);
-                if (c1 >= 0) h1 = test_bit(front, c1);
-                if (c2 >= 0) h2 = test_bit(front, c2);
-                if (c3 >= 0) h3 = test_bit(front, c3);
-                if (live) {
-                    if (h0) { found = true; par = c0; }
-                    else if (h1) { found = true; par = c1; }
-                    else if (h2) { found = true; par = c2; }
-                    else if (h3) { found = true; par = c3; }
-                    if (found || s + p0 + 4 >= e) live = false;
-                }
+            unsigned long long seen[2], vw[2];
+            long long v[2];
+            bool act[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                seen[j] = wi[j] >= 0 ? bcast_u64(vwl | fwl, wi[j]) : ~0ull;
+                vw[j] = wi[j] >= 0 ? bcast_u64(vwl, wi[j]) : ~0ull;
+                v[j] = ((base + (wi[j] >= 0 ? wi[j] : 0)) << 6) + lane;
+                act[j] = !((seen[j] >> lane) & 1ull);
             }
-            unsigned long long rem = __ballot(act && !found && s + K < e);
-            while (rem) {
-                const int k = __ffsll((long long)rem) - 1;
-                rem &= rem - 1;
-                const long long sk = bcast64(s, k) + K;
-                const long long ek = bcast64(e, k);
-                int hitv = -1;
-                for (long long b = sk; b < ek; b += 64) {
-                    const long long j = b + lane;
-                    int u = 0;
-                    bool hit = false;
-                    if (j < ek) {
-                        u = P.col[j];
-                        hit = test_bit(front, u);
+            // phase 1a for both vertices: degree and slab loads together
+            int dg[2], c[2][4];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                dg[j] = act[j] ? P.deg[v[j]] : 0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    c[j][p] = (act[j] && p < KS) ? P.slab[(long long)p * P.n + v[j]] : -1;
+            }
+            bool found[2];
+            int par[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                bool h[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) h[p] = c[j][p] >= 0 && test_bit(front, c[j][p]);
+                found[j] = false;
+                par[j] = -1;
+#pragma unroll
+                for (int p = 3; p >= 0; --p)
+                    if (h[p]) {
+                        found[j] = true;
+                        par[j] = c[j][p];
                     }
-                    const unsigned long long hb = __ballot(hit);
-                    if (hb) {
-                        hitv = __builtin_amdgcn_readlane(u, __ffsll((long long)hb) - 1);
-                        break;
-                    }
-                }
-                if (hitv >= 0 && lane == k) {
-                    found = true;
-                    par = hitv;
-                }
             }
-            const unsigned long long fm = __ballot(found);
-            if (found) {
-                P.level[v] = d + 1;
-                P.parent[v] = par;
-                nf += 1;
-                mf += (unsigned long long)(e - s);
-            }
-            // `next` was cleared one layer ahead: store only nonzero words
-            if (lane == 0) {
-                if (fm) next[w] = fm;
-                if ((seen | fm) != vw) P.vis[w] = seen | fm;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (wi[j] < 0) continue;
+                bu_finish_vertex(P, front, v[j], act[j], dg[j], KS, K, found[j], par[j]);
+                const unsigned long long fm = __ballot(found[j]);
+                if (found[j]) {
+                    P.level[v[j]] = d + 1;
+                    P.parent[v[j]] = par[j];
+                    nf += 1;
+                    mf += (unsigned long long)dg[j];
+                    nh += dg[j] > P.hub_deg;
+                }
+                // `next` was cleared one layer ahead: store only nonzero words
+                if (lane == 0) {
+                    const long long w = base + wi[j];
+                    if (fm) next[w] = fm;
+                    if ((seen[j] | fm) != vw[j]) P.vis[w] = seen[j] | fm;
+                }
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-__device__ void flush_counters(unsigned long long nf, unsigned long long mf, Slot *slot,
-                               unsigned long long *s_red, int nwaves_block)
+__device__ void flush_counters(unsigned long long nf, unsigned long long mf, unsigned long long nh,
+                               Slot *slot, unsigned long long *s_red, int nwaves_block)
 {
+    unsigned long long *sub = slot->c[blockIdx.x % kSub];
     const int lane = __lane_id();
     const int wib = threadIdx.x >> 6;
     nf = wave_sum_u64(nf);
     mf = wave_sum_u64(mf);
+    nh = wave_sum_u64(nh);
     if (lane == 0) {
-        s_red[2 * wib] = nf;
-        s_red[2 * wib + 1] = mf;
+        s_red[3 * wib] = nf;
+        s_red[3 * wib + 1] = mf;
+        s_red[3 * wib + 2] = nh;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0, b = 0;
+        unsigned long long a = 0, b = 0, c = 0;
         for (int i = 0; i < nwaves_block; ++i) {
-            a += s_red[2 * i];
-            b += s_red[2 * i + 1];
+            a += s_red[3 * i];
+            b += s_red[3 * i + 1];
+            c += s_red[3 * i + 2];
         }
-        if (a) atomicAdd(&slot->n_f, a);
-        if (b) atomicAdd(&slot->m_f, b);
+        if (a) atomicAdd(&sub[0], a);
+        if (b) atomicAdd(&sub[1], b);
+        if (c) atomicAdd(&sub[2], c);
     }
     __syncthreads();
 }
 
-// One layer (the body of Algorithm 3's loop).  Returns false once the BFS is
-// complete.  `leader` is the one thread that writes shared control state.
+// Control data a block reads at the start of a layer.  It was written by
+// earlier kernels (or, in the finisher, by this block before a barrier), so
+// plain loads see it; thread 0 loads it once and the block shares it.
+struct LayerView {
+    int done;
+    int pad;
+    int *level;
+    int *parent;
+    LayerState S;
+    long long n_f, m_f, n_h;
+};
+
 __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long long nwaves,
                           long long gt, long long nt, bool leader, unsigned long long *s_red,
-                          int nwaves_block)
+                          int nwaves_block, LayerView *view, bool same_kernel, int d_hint)
 {
     Ctrl *C = Pin.ctrl;
-    if (__hip_atomic_load(&C->done, __ATOMIC_RELAXED, AGENT)) return false;
+    if (threadIdx.x == 0) {
+        view->done = C->done;
+        view->level = C->level;
+        view->parent = C->parent;
+        view->S = C->st[parity];
+        // kernel i of the launch sequence handles layer i, so its counter slot is
+        // known without waiting for the state load; the finisher passes -1
+        Slot &sl = C->slot[(d_hint >= 0 ? d_hint : view->S.d) % kSlots];
+        long long a = 0, b = 0, c = 0;
+        for (int k = 0; k < kSub; ++k) {
+            // counters added by atomics earlier in this same kernel (finisher)
+            // are read at the device-coherent level, past any stale L1 line
+            a += (long long)(same_kernel ? ld_relaxed(&sl.c[k][0]) : sl.c[k][0]);
+            b += (long long)(same_kernel ? ld_relaxed(&sl.c[k][1]) : sl.c[k][1]);
+            c += (long long)(same_kernel ? ld_relaxed(&sl.c[k][2]) : sl.c[k][2]);
+        }
+        view->n_f = a;
+        view->m_f = b;
+        view->n_h = c;
+    }
+    __syncthreads();
+    if (view->done) return false;
     // the outputs of this traversal were recorded by the init kernel
     Params P = Pin;
-    P.level = C->level;
-    P.parent = C->parent;
-    const LayerState S = C->st[parity];
+    P.level = view->level;
+    P.parent = view->parent;
+    const LayerState S = view->S;
     const int d = S.d;
-    const long long n_f = (long long)ld_relaxed(&C->slot[d % kSlots].n_f);
-    const long long m_f = (long long)ld_relaxed(&C->slot[d % kSlots].m_f);
+    if (d_hint >= 0 && d != d_hint) {
+        // the launch sequence and the device state disagree: a host-side bug
+        if (leader) atomicOr((unsigned *)&C->status, 16u);
+        return false;
+    }
+    const long long n_f = view->n_f;
+    const long long m_f = view->m_f;
     long long m_u = S.m_u, v_u = S.v_u;
     m_u -= m_f;
     v_u -= n_f;
     if (d > P.n) {
         // a BFS has at most n layers; stop with an error rather than loop
-        if (leader) __hip_atomic_store(&C->done, 2, __ATOMIC_RELAXED, AGENT);
+        if (leader) C->done = 2;
         return false;
     }
     if (n_f == 0) {
@@ -318,8 +543,8 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
             C->nlayers = d;
             C->reached = S.reached;
             C->reached_deg = S.reached_deg;
-            C->t_end = (unsigned long long)wall_clock64();
-            __hip_atomic_store(&C->done, 1, __ATOMIC_RELAXED, AGENT);
+            C->t_end = 0ull;
+            C->done = 1;
         }
         return false;
     }
@@ -333,7 +558,10 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
             r.m_f = m_f;
             r.m_u = m_u;
             r.v_u = v_u;
-            r.t = (unsigned long long)wall_clock64();
+            // no device clock read here: a kernel that merely contains one
+            // (even on a branch not taken) was measured about 10 us slower per
+            // launch on gfx950; per-layer times come from HIP events instead
+            r.t = 0ull;
             P.trace[d] = r;
         }
         LayerState Nx = S;
@@ -346,17 +574,20 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
         C->st[parity ^ 1] = Nx;
         C->parity = parity ^ 1;
         Slot *Z = &C->slot[(d + 2) % kSlots];
-        Z->n_f = 0;
-        Z->m_f = 0;
+        for (int k = 0; k < kSub; ++k) {
+            Z->c[k][0] = 0;
+            Z->c[k][1] = 0;
+            Z->c[k][2] = 0;
+        }
     }
     unsigned long long *front = P.bm + (long long)(d % 3) * P.W;
     unsigned long long *next = P.bm + (long long)((d + 1) % 3) * P.W;
     unsigned long long *spare = P.bm + (long long)((d + 2) % 3) * P.W;
-    unsigned long long nf = 0, mf = 0;
-    if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, gwave, nwaves);
-    else bottom_up_step(P, d, front, next, nf, mf, gwave, nwaves);
+    unsigned long long nf = 0, mf = 0, nh = 0;
+    if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, view->n_h > 0, gwave, nwaves);
+    else bottom_up_step(P, d, front, next, nf, mf, nh, gwave, nwaves);
     for (long long w = gt; w < P.W; w += nt) spare[w] = 0ull;   // `next` of layer d+1
-    flush_counters(nf, mf, &C->slot[(d + 1) % kSlots], s_red, nwaves_block);
+    flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, nwaves_block);
     return true;
 }
 
@@ -417,37 +648,43 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
         S.pad[0] = S.pad[1] = S.pad[2] = 0;
         C->st[0] = S;
         C->st[1] = S;
-        for (int k = 0; k < kSlots; ++k) {
-            C->slot[k].n_f = k == 0 ? 1ull : 0ull;
-            C->slot[k].m_f = k == 0 ? (unsigned long long)deg_r : 0ull;
-        }
+        C->status = 0;
+        for (int k = 0; k < kSlots; ++k)
+            for (int j = 0; j < kSub; ++j) {
+                C->slot[k].c[j][0] = (k == 0 && j == 0) ? 1ull : 0ull;
+                C->slot[k].c[j][1] = (k == 0 && j == 0) ? (unsigned long long)deg_r : 0ull;
+                C->slot[k].c[j][2] = (k == 0 && j == 0 && deg_r > P.hub_deg) ? 1ull : 0ull;
+            }
     }
 }
 
-__global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int parity)
+__global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer)
 {
-    __shared__ unsigned long long s_red[2 * kWavesPerBlock];
+    const int parity = layer & 1;
+    __shared__ unsigned long long s_red[3 * kWavesPerBlock];
+    __shared__ LayerView view;
     const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
     run_layer(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
-              kWavesPerBlock);
+              kWavesPerBlock, &view, false, layer);
 }
 
 // One block runs whatever layers remain, with block barriers between them.
 __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
 {
-    __shared__ unsigned long long s_red[2 * (kFinishBlock / 64)];
+    __shared__ unsigned long long s_red[3 * (kFinishBlock / 64)];
     __shared__ int s_parity;
+    __shared__ LayerView view;
     const long long gwave = threadIdx.x >> 6;
     const long long nwaves = kFinishBlock / 64;
     for (;;) {
-        if (threadIdx.x == 0) s_parity = __hip_atomic_load(&P.ctrl->parity, __ATOMIC_RELAXED, AGENT);
+        if (threadIdx.x == 0) s_parity = P.ctrl->parity;
         __syncthreads();
         const int parity = s_parity;
         if (!run_layer(P, parity, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, s_red,
-                       kFinishBlock / 64))
+                       kFinishBlock / 64, &view, true, -1))
             break;
         __syncthreads();
     }
@@ -473,9 +710,9 @@ hipError_t launch_init(const Params &p, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_layer(const Params &p, int parity, int grid, hipStream_t s)
+hipError_t launch_layer(const Params &p, int layer, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(bfs_layer_kernel, dim3(grid), dim3(kBlock), 0, s, p, parity);
+    hipLaunchKernelGGL(bfs_layer_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer);
     return hipGetLastError();
 }
 

@@ -92,8 +92,9 @@ int validate_options(const bfs_options &o)
         return set_error(BFS_E_INVALID, "words_per_wave must be 0 or a power of two <= 64");
     if (o.layers_per_launch < 0 || o.layers_per_launch > 4096)
         return set_error(BFS_E_INVALID, "layers_per_launch must be in [0, 4096]");
-    for (int r : o.reserved)
-        if (r) return set_error(BFS_E_INVALID, "reserved option fields must be zero");
+    if (o.graph_launch < 0 || o.graph_launch > 1 || o.profile_layers < 0 || o.profile_layers > 1 ||
+        o.async < 0 || o.async > 1 || o.out_on_device < 0 || o.out_on_device > 1)
+        return set_error(BFS_E_INVALID, "flag options must be 0 or 1");
     return BFS_OK;
 }
 
@@ -106,6 +107,11 @@ Workspace::~Workspace()
     if (h_trace) hipHostFree(h_trace);
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
+    for (hipEvent_t e : layer_ev) hipEventDestroy(e);
+    for (auto &kv : replays) {
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+    }
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -160,13 +166,19 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->off = g->d_off;
     P->col = g->d_col;
     P->iso = g->d_iso;
+    P->deg = g->d_deg;
+    P->slab = g->d_slab;
+    P->slab_k = g->slab_k;
+    P->chunk_log2 = kChunkLog2;
     P->hub = g->d_hub;
     P->n_hub = g->n_hub;
-    P->hub_log2 = kHubLog2;
-    P->hub_deg = kHubDegree;
-    P->small_deg = std::min(opt.small_degree, kHubDegree);
+    P->hub_deg = g->hub_deg;
+    P->small_deg = opt.small_degree;
     P->probe_k = opt.probe_k;
     P->wpg = opt.words_per_wave > 0 ? opt.words_per_wave : g->wpg_default;
+    // top-down work is per frontier vertex, so its scan uses wide tasks: a
+    // sparse frontier then costs one load per 64 words
+    P->wpg_td = 64;
     P->vis = w->vis;
     P->bm = w->bm;
     P->ctrl = w->ctrl;
@@ -175,10 +187,11 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->rule = opt.rule;
     P->alpha = opt.alpha;
     P->beta = opt.beta;
+    P->timing = opt.profile_layers;
 }
 
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
-                      hipStream_t s, int *layers_enqueued)
+                      hipStream_t s, int *layers_enqueued, bool profile)
 {
     Params P;
     fill_params(g, w, opt, &P);
@@ -188,23 +201,110 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->typical_layers.load();
     hipError_t e;
+    if (profile) {
+        while ((int)w->layer_ev.size() < 2 * L) {
+            hipEvent_t ev;
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "event");
+            w->layer_ev.push_back(ev);
+        }
+    }
     if ((e = launch_init(P, grid, s)) != hipSuccess) return hip_fail(e, "init launch");
-    for (int i = 0; i < L; ++i)
-        if ((e = launch_layer(P, i & 1, grid, s)) != hipSuccess) return hip_fail(e, "layer launch");
+    for (int i = 0; i < L; ++i) {
+        if (profile && (e = hipEventRecord(w->layer_ev[2 * i], s)) != hipSuccess) return hip_fail(e, "event");
+        if ((e = launch_layer(P, i, grid, s)) != hipSuccess) return hip_fail(e, "layer launch");
+        if (profile && (e = hipEventRecord(w->layer_ev[2 * i + 1], s)) != hipSuccess) return hip_fail(e, "event");
+    }
     if ((e = launch_finish(P, s)) != hipSuccess) return hip_fail(e, "finisher launch");
     if (layers_enqueued) *layers_enqueued = L;
     return BFS_OK;
 }
 
-static double ticks_to_us(const Graph *g, unsigned long long t) { return (double)t / g->wall_ticks_per_us; }
+// hipGraph replay of the launch sequence [init, L x layer, finisher].  The
+// graph is built once per workspace and option set; a run only rewrites the
+// init node's arguments (root and output pointers), which the layer kernels
+// pick up from the control block.
+int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl,
+                            int *par, hipStream_t s, int *layers_enqueued)
+{
+    Params P;
+    fill_params(g, w, opt, &P);
+    const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
+    const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->typical_layers.load();
+    char key[160];
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k, P.wpg,
+             P.wpg_td, grid, L);
+    hipError_t e;
+    auto it = w->replays.find(key);
+    if (it == w->replays.end()) {
+        Workspace::Replay R;
+        R.params = P;
+        R.params.root = root;
+        R.params.level = lvl;
+        R.params.parent = par;
+        if ((e = hipGraphCreate(&R.graph, 0)) != hipSuccess) return hip_fail(e, "graph create");
+        std::vector<int> layer_idx(L);
+        for (int i = 0; i < L; ++i) layer_idx[i] = i;
+        hipGraphNode_t prev = nullptr;
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof kp);
+        void *init_args[] = {&R.params};
+        kp.func = kernel_ptr_init();
+        kp.gridDim = dim3(grid);
+        kp.blockDim = dim3(kBlock);
+        kp.kernelParams = init_args;
+        if ((e = hipGraphAddKernelNode(&R.init, R.graph, nullptr, 0, &kp)) != hipSuccess)
+            return hip_fail(e, "graph init node");
+        prev = R.init;
+        for (int i = 0; i < L; ++i) {
+            void *args[] = {&R.params, &layer_idx[i]};
+            kp.func = kernel_ptr_layer();
+            kp.kernelParams = args;
+            hipGraphNode_t node;
+            if ((e = hipGraphAddKernelNode(&node, R.graph, &prev, 1, &kp)) != hipSuccess)
+                return hip_fail(e, "graph layer node");
+            prev = node;
+        }
+        void *fin_args[] = {&R.params};
+        kp.func = kernel_ptr_finish();
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(kFinishBlock);
+        kp.kernelParams = fin_args;
+        hipGraphNode_t fin;
+        if ((e = hipGraphAddKernelNode(&fin, R.graph, &prev, 1, &kp)) != hipSuccess)
+            return hip_fail(e, "graph finisher node");
+        if ((e = hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0)) != hipSuccess)
+            return hip_fail(e, "graph instantiate");
+        it = w->replays.emplace(key, R).first;
+    }
+    Workspace::Replay &R = it->second;
+    R.params.root = root;
+    R.params.level = lvl;
+    R.params.parent = par;
+    void *init_args[] = {&R.params};
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.func = kernel_ptr_init();
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(kBlock);
+    kp.kernelParams = init_args;
+    if ((e = hipGraphExecKernelNodeSetParams(R.exec, R.init, &kp)) != hipSuccess)
+        return hip_fail(e, "graph update");
+    if ((e = hipGraphLaunch(R.exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    if (layers_enqueued) *layers_enqueued = L;
+    return BFS_OK;
+}
 
-// Adaptive layer count: enough for the deepest traversal seen recently, so
-// the single-block finisher only runs for unusually deep ones.
+
+// Adaptive layer count: the deepest of the last 16 traversals.  A traversal of
+// that depth ends in the single-block finisher, which only has to see the
+// empty frontier; deeper ones are finished there.
 static void note_depth(Graph *g, int nlayers)
 {
-    int want = std::min(std::max(nlayers + 1, 4), 64);
-    int cur = g->typical_layers.load();
-    if (want > cur) g->typical_layers.compare_exchange_strong(cur, want);
+    const unsigned pos = g->recent_pos.fetch_add(1) % 16;
+    g->recent_depth[pos].store(nlayers);
+    int mx = 0;
+    for (int i = 0; i < 16; ++i) mx = std::max(mx, g->recent_depth[i].load());
+    g->typical_layers.store(std::min(std::max(mx, 2), 64));
 }
 
 }  // namespace hybfs
@@ -295,27 +395,66 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     g->n = n;
     g->nnz = nnz;
     g->W = (n + 63) >> 6;
-    // per-vertex summaries and the top-down hub-chunk table (a1 precompute)
-    std::vector<Item> hub;
+    // per-vertex data every traversal reads: degrees and the position-major
+    // slab of each row's first slab_k entries (-1 past the end of the row)
+    g->slab_k = n <= (1LL << 25) ? 4 : 2;
+    std::vector<int32_t> deg, slab;
+    try {
+        deg.resize((size_t)n);
+        slab.assign((size_t)n * g->slab_k, -1);
+    } catch (...) {
+        return set_error(BFS_E_NOMEM, "host staging of per-vertex data");
+    }
     int64_t iso = 0, maxd = 0;
     for (int64_t v = 0; v < n; ++v) {
         const int64_t dv = h_off[v + 1] - h_off[v];
+        if (dv > 0x7FFFFFFF) return set_error(BFS_E_INVALID, "degree of vertex %lld exceeds 2^31-1", (long long)v);
+        deg[v] = (int32_t)dv;
         iso += dv == 0;
         maxd = std::max(maxd, dv);
-        if (dv > kHubDegree) {
-            const int64_t k = (dv + (1 << kHubLog2) - 1) >> kHubLog2;
-            for (int64_t c = 0; c < k; ++c) hub.push_back(Item{(int)v, (int)c});
+    }
+    if (nnz > 0) {
+        // the columns may only be on the device (unvalidated device input)
+        std::vector<int32_t> tmp;
+        const int32_t *cols = h_col;
+        if (!cols) {
+            try {
+                tmp.resize((size_t)nnz);
+            } catch (...) {
+                return set_error(BFS_E_NOMEM, "host staging of columns");
+            }
+            if ((e = hipMemcpy(tmp.data(), col_indices, nnz * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+                return hip_fail(e, "reading device col_indices");
+            cols = tmp.data();
         }
+        for (int64_t v = 0; v < n; ++v)
+            for (int p = 0; p < g->slab_k && p < deg[v]; ++p) slab[(size_t)p * n + v] = cols[h_off[v] + p];
     }
     g->isolated = iso;
     g->max_degree = maxd;
-    g->n_hub = (long long)hub.size();
+    // top-down hub table: every 256-edge chunk of each vertex above hub_deg
+    std::vector<Item> hub;
+    {
+        const int64_t H = kHubDegree;
+        g->hub_deg = (int)H;
+        for (int64_t v = 0; v < n; ++v)
+            if (deg[v] > H) {
+                const int64_t k = ((int64_t)deg[v] + (1 << kChunkLog2) - 1) >> kChunkLog2;
+                for (int64_t c = 0; c < k; ++c) hub.push_back(Item{(int)v, (int)c});
+            }
+        g->n_hub = (long long)hub.size();
+    }
 
     if ((e = hipMalloc(&g->d_off, (n + 1) * 8)) != hipSuccess) return hip_fail(e, "graph offsets");
     if ((e = hipMalloc(&g->d_col, std::max<int64_t>(nnz, 1) * 4)) != hipSuccess) return hip_fail(e, "graph columns");
     if ((e = hipMalloc(&g->d_iso, g->W * 8)) != hipSuccess) return hip_fail(e, "graph bitmap");
+    if ((e = hipMalloc(&g->d_deg, n * 4)) != hipSuccess) return hip_fail(e, "degrees");
+    if ((e = hipMalloc(&g->d_slab, n * 4 * g->slab_k)) != hipSuccess) return hip_fail(e, "slab");
     if ((e = hipMalloc(&g->d_hub, std::max<size_t>(hub.size(), 1) * sizeof(Item))) != hipSuccess)
         return hip_fail(e, "hub table");
+    if (!hub.empty() &&
+        (e = hipMemcpy(g->d_hub, hub.data(), hub.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "upload hub table");
     e = hipMemcpy(g->d_off, h_off, (n + 1) * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload offsets");
     if (nnz > 0) {
@@ -324,27 +463,26 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
                       from_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "upload columns");
     }
-    if (!hub.empty()) {
-        e = hipMemcpy(g->d_hub, hub.data(), hub.size() * sizeof(Item), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "upload hub table");
-    }
+    if ((e = hipMemcpy(g->d_deg, deg.data(), n * 4, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "upload degrees");
+    if ((e = hipMemcpy(g->d_slab, slab.data(), n * 4 * g->slab_k, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "upload slab");
     if ((e = launch_iso_template(g->d_off, n, g->W, g->d_iso, 0)) != hipSuccess) return hip_fail(e, "iso kernel");
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "graph setup");
 
-    int cus = 0, rate_khz = 0;
+    int cus = 0;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->dev);
-    hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g->dev);
     const int per_cu = layer_blocks_per_cu();
     if (per_cu < 1 || cus < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
     g->cus = cus;
     g->blocks_per_cu = per_cu;
-    g->grid_default = per_cu * cus;
+    g->grid_default = std::min(per_cu, 4) * cus;
     // size a wavefront task so that about two tasks fall on each resident wave
     const long long resident_waves = (long long)g->grid_default * kWavesPerBlock;
     int wpg = 1;
     while (wpg < 64 && (g->W + wpg - 1) / wpg > 2 * resident_waves) wpg <<= 1;
     g->wpg_default = wpg;
-    g->wall_ticks_per_us = rate_khz > 0 ? rate_khz / 1000.0 : 100.0;
+    for (int i = 0; i < 16; ++i) g->recent_depth[i].store(9);
     *out = reinterpret_cast<bfs_graph_t>(g.release());
     return BFS_OK;
 }
@@ -360,6 +498,8 @@ int bfs_graph_destroy(bfs_graph_t gh)
     if (g->d_off) hipFree(g->d_off);
     if (g->d_col) hipFree(g->d_col);
     if (g->d_iso) hipFree(g->d_iso);
+    if (g->d_deg) hipFree(g->d_deg);
+    if (g->d_slab) hipFree(g->d_slab);
     if (g->d_hub) hipFree(g->d_hub);
     delete g;
     return BFS_OK;
@@ -375,12 +515,15 @@ int bfs_graph_info_get(bfs_graph_t gh, bfs_graph_info *info)
     info->nnz = g->nnz;
     info->isolated = g->isolated;
     info->max_degree = g->max_degree;
-    info->device_bytes = (g->n + 1) * 8 + g->nnz * 4 + g->W * 8 + g->n_hub * (int64_t)sizeof(Item);
+    info->device_bytes = (g->n + 1) * 8 + g->nnz * 4 + g->W * 8 + g->n * 4 * (1 + g->slab_k) +
+                         g->n_hub * (int64_t)sizeof(Item);
     info->workspace_bytes = (int64_t)workspace_bytes(g->W);
     info->grid_blocks = g->grid_default;
     info->block_threads = kBlock;
+    info->slab_k = g->slab_k;
+    info->chunk_edges = 1 << kChunkLog2;
+    info->hub_degree = g->hub_deg;
     info->hub_chunks = g->n_hub;
-    info->hub_degree = kHubDegree;
     info->typical_layers = g->typical_layers.load();
     return BFS_OK;
 }
@@ -425,8 +568,13 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
         par = w->out_tmp + ((g->n + 63) & ~63LL);
     }
 
+    const bool profile = opt.profile_layers && stats && !opt.async;
+    int launched = 0;
     if ((e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
-    rc = enqueue_traversal(g, w, opt, root, lvl, par, s, nullptr);
+    if (!opt.graph_launch || profile)
+        rc = enqueue_traversal(g, w, opt, root, lvl, par, s, &launched, profile);
+    else
+        rc = enqueue_traversal_graph(g, w, opt, root, lvl, par, s, &launched);
     if (rc) return rc;
     if ((e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
     if (opt.async) return BFS_OK;
@@ -440,7 +588,10 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "traversal");
     const Ctrl &c = *w->h_ctrl;
-    if (c.done != 1) return set_error(BFS_E_DEVICE, "traversal did not complete (state %d)", c.done);
+    if (c.done != 1 || c.status != 0) {
+        return set_error(BFS_E_DEVICE, "traversal failed a device-side check (done %d, status %d)",
+                         c.done, c.status);
+    }
     note_depth(g, c.nlayers);
     if (stats) {
         stats->num_layers = c.nlayers;
@@ -449,6 +600,18 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
         float ms = 0.f;
         hipEventElapsedTime(&ms, w->e0, w->e1);
         stats->device_us = ms * 1000.0;
+        stats->layer_launches = launched;
+        stats->reserved = 0;
+        stats->layer_kernel_us = 0.0;
+        std::vector<double> kus(launched, 0.0);
+        if (profile) {
+            for (int i = 0; i < launched; ++i) {
+                float lm = 0.f;
+                hipEventElapsedTime(&lm, w->layer_ev[2 * i], w->layer_ev[2 * i + 1]);
+                kus[i] = lm * 1000.0;
+                stats->layer_kernel_us += kus[i];
+            }
+        }
         const int nrec = std::min(c.nlayers, kTraceCap);
         if (stats->layers && stats->capacity > 0 && nrec > 0) {
             const int ncopy = std::min(nrec, stats->capacity);
@@ -463,8 +626,8 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
                 o.m_f = r.m_f;
                 o.m_u = r.m_u;
                 o.v_u = r.v_u;
-                const unsigned long long tn = (i + 1 < nrec) ? w->h_trace[i + 1].t : c.t_end;
-                o.t_us = ticks_to_us(g, tn - r.t);
+                o.kernel_us = (profile && i < launched) ? kus[i] : 0.0;
+                o.t_us = o.kernel_us;
             }
         }
     }

@@ -7,6 +7,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "../../include/hybfs.h"
 #include "bfs_device.h"
@@ -14,8 +16,8 @@
 namespace hybfs {
 
 constexpr int kTraceCap = 4096;      // per-layer trace records kept on the device
-constexpr int kHubDegree = 512;      // top-down: above this a vertex's edges go to the hub table
-constexpr int kHubLog2 = 9;          // ... in chunks of 512 edges
+constexpr int kChunkLog2 = 8;        // top-down hub chunks cover 256 edges
+constexpr int kHubDegree = 256;      // top-down: above this degree, edges go through the hub table
 
 // Per-stream scratch of a single-root traversal.
 struct Workspace {
@@ -31,6 +33,15 @@ struct Workspace {
     Ctrl *h_ctrl = nullptr;       // pinned
     LayerRec *h_trace = nullptr;  // pinned
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<hipEvent_t> layer_ev;   // profile_layers: start/end per layer kernel
+    // captured launch sequences: key = option set and layer count
+    struct Replay {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t init = nullptr;
+        Params params;
+    };
+    std::map<std::string, Replay> replays;
     ~Workspace();
 };
 
@@ -40,15 +51,20 @@ struct Graph {
     long long *d_off = nullptr;
     int *d_col = nullptr;
     unsigned long long *d_iso = nullptr;
-    Item *d_hub = nullptr;
+    int *d_deg = nullptr;
+    int *d_slab = nullptr;
+    int slab_k = 0;
+    Item *d_hub = nullptr;        // top-down chunks of vertices above hub_deg
     long long n_hub = 0;
+    int hub_deg = 0;
     long long isolated = 0, max_degree = 0;
     int cus = 0;
     int blocks_per_cu = 0;
     int grid_default = 0;
     int wpg_default = 1;
-    double wall_ticks_per_us = 100.0;
     std::atomic<int> typical_layers{10};
+    std::atomic<int> recent_depth[16];   // depths of the last traversals (ring)
+    std::atomic<unsigned> recent_pos{0};
     std::mutex mu;
     std::map<void *, std::unique_ptr<Workspace>> ws;
 };
@@ -63,6 +79,6 @@ int check_csr(int64_t n, int64_t nnz, const int64_t *off, const int32_t *col, bo
 int get_workspace(Graph *g, void *stream, Workspace **out);
 void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P);
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
-                      hipStream_t s, int *layers_enqueued);
+                      hipStream_t s, int *layers_enqueued, bool profile);
 
 }  // namespace hybfs

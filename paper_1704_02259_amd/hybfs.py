@@ -37,28 +37,31 @@ class bfs_options(ctypes.Structure):
                 ("probe_k", ctypes.c_int32), ("small_degree", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("words_per_wave", ctypes.c_int32),
                 ("layers_per_launch", ctypes.c_int32), ("out_on_device", ctypes.c_int32),
-                ("async_", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
-                ("stream", ctypes.c_void_p)]
+                ("async_", ctypes.c_int32), ("profile_layers", ctypes.c_int32),
+                ("graph_launch", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class bfs_layer_stat(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("n_f", ctypes.c_int64), ("m_f", ctypes.c_int64), ("m_u", ctypes.c_int64),
-                ("v_u", ctypes.c_int64), ("t_us", ctypes.c_double)]
+                ("v_u", ctypes.c_int64), ("t_us", ctypes.c_double), ("kernel_us", ctypes.c_double)]
 
 
 class bfs_stats(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int32), ("num_layers", ctypes.c_int32),
                 ("layers", ctypes.POINTER(bfs_layer_stat)), ("reached", ctypes.c_int64),
-                ("reached_degree_sum", ctypes.c_int64), ("device_us", ctypes.c_double)]
+                ("reached_degree_sum", ctypes.c_int64), ("device_us", ctypes.c_double),
+                ("layer_launches", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("layer_kernel_us", ctypes.c_double)]
 
 
 class bfs_graph_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("isolated", ctypes.c_int64),
                 ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("grid_blocks", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("hub_chunks", ctypes.c_int64),
-                ("hub_degree", ctypes.c_int32), ("typical_layers", ctypes.c_int32)]
+                ("block_threads", ctypes.c_int32), ("slab_k", ctypes.c_int32),
+                ("chunk_edges", ctypes.c_int32), ("typical_layers", ctypes.c_int32),
+                ("hub_degree", ctypes.c_int32), ("hub_chunks", ctypes.c_int64)]
 
 
 class HybfsError(RuntimeError):
@@ -159,7 +162,7 @@ def stats_layers(st: bfs_stats, arr) -> list[dict]:
     for i in range(min(st.num_layers, st.capacity)):
         r = arr[i]
         out.append({"dir": r.direction, "n_f": r.n_f, "m_f": r.m_f, "m_u": r.m_u, "v_u": r.v_u,
-                    "t_us": r.t_us})
+                    "t_us": r.t_us, "kernel_us": r.kernel_us})
     return out
 
 
@@ -216,5 +219,7 @@ class Graph:
         if stats:
             return level, parent, {"num_layers": st.num_layers, "reached": st.reached,
                                    "reached_degree_sum": st.reached_degree_sum,
-                                   "device_us": st.device_us, "layers": stats_layers(st, arr)}
+                                   "device_us": st.device_us, "layer_launches": st.layer_launches,
+                                   "layer_kernel_us": st.layer_kernel_us,
+                                   "layers": stats_layers(st, arr)}
         return level, parent

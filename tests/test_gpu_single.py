@@ -88,7 +88,7 @@ def test_kron16_parameters_do_not_change_output(torch, kron16, probe_k, small, g
     g, G, roots = kron16
     r = int(roots[0])
     kw = dict(probe_k=probe_k, small_degree=small, grid_blocks=grid, words_per_wave=wpw,
-              layers_per_launch=layers)
+              layers_per_launch=layers, graph_launch=layers % 2)
     _say("kron16 params", kw)
     lv, pa, st = _gpu_bfs(torch, G, r, **kw)
     _check_against_oracle(g, r, lv, pa, st)
@@ -231,3 +231,41 @@ def test_kron20_all_roots_invariants(torch, kron20):
             lv0 = lv
         # every root of degree > 0 in the giant component reaches the same set
         assert st["reached"] == int((lv >= 0).sum())
+
+
+def test_graph_replay_alternating_roots_and_buffers(torch, kron16):
+    """The captured launch sequence (graph_launch=1) is replayed with a new root
+    and new output buffers each time; every replay must match the oracle, as
+    must the direct (kernel-by-kernel) launch."""
+    g, G, roots = kron16
+    bufs = [(torch.empty(g.n, dtype=torch.int32, device="cuda"),
+             torch.empty(g.n, dtype=torch.int32, device="cuda")) for _ in range(3)]
+    expected = {int(r): oracle.bfs(g, int(r)) for r in roots}
+    for it in range(9):
+        r = int(roots[it % len(roots)])
+        lv, pa = bufs[it % 3]
+        G.run(r, lv, pa, graph_launch=1)
+        torch.cuda.synchronize()
+        assert np.array_equal(lv.cpu().numpy(), expected[r][0]), (it, r)
+        assert np.array_equal(pa.cpu().numpy(), expected[r][1]), (it, r)
+    for r in roots:
+        lv, pa, st = _gpu_bfs(torch, G, int(r), graph_launch=0)
+        _check_against_oracle(g, int(r), lv, pa, st)
+
+
+def test_async_runs_back_to_back(torch, kron16):
+    """Asynchronous runs enqueued back to back on one stream, each into its own
+    buffers, then one synchronisation."""
+    g, G, roots = kron16
+    s = torch.cuda.Stream()
+    outs = []
+    for r in list(roots) * 2:
+        lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        pa = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        G.run(int(r), lv, pa, stream=s.cuda_stream, async_=1)
+        outs.append((int(r), lv, pa))
+    from paper_1704_02259_amd import hybfs
+    hybfs.bfs_graph_sync(G.handle, s.cuda_stream)
+    for r, lv, pa in outs:
+        elv, epa = oracle.bfs(g, r)
+        assert np.array_equal(lv.cpu().numpy(), elv) and np.array_equal(pa.cpu().numpy(), epa)
