@@ -94,6 +94,9 @@ typedef struct bfs_graph_info {
     int32_t hub_degree;      /* top-down: vertices above this degree are expanded
                                 through a grid-wide table of edge chunks */
     int64_t hub_chunks;      /* entries of that table */
+    int64_t batch_workspace_bytes; /* device bytes of one batched workspace
+                                      (bfs_run_batch), excluding host-output
+                                      staging */
 } bfs_graph_info;
 
 int bfs_graph_info_get(bfs_graph_t g, bfs_graph_info *info);
@@ -191,6 +194,36 @@ typedef struct bfs_stats {
  */
 int bfs_run(bfs_graph_t g, int32_t root, int32_t *level_out, int32_t *parent_out,
             const bfs_options *opt, bfs_stats *stats);
+
+/*
+ * Batched multi-source BFS: k independent single-root traversals sharing one
+ * pass over the adjacency lists per layer.  Roots are taken in groups of 64;
+ * within a group, bit b of a per-vertex 64-bit mask stands for root b, so the
+ * frontier of every root is expanded (Algorithm 1) or probed (Algorithm 2) by
+ * one read of each row, and one direction decision (Algorithm 3, edge rule on
+ * counts over the union of the roots' frontiers) covers the whole group.  The
+ * result for root i is exactly what bfs_run(roots[i]) returns, bit for bit.
+ *   roots                 int32[k] host array, each in [0, n); repeats allowed.
+ *   k                     >= 1.
+ *   level_out, parent_out int32[k * n] each, root-major: root i's arrays start
+ *                         at element i * n.  Device pointers if
+ *                         opt->out_on_device, else host pointers.
+ *   opt                   as for bfs_run, except: rule must be BFS_RULE_EDGES,
+ *                         BFS_RULE_TOPDOWN or BFS_RULE_BOTTOMUP; graph_launch
+ *                         must be 0; probe_k is not used (the pull scans each
+ *                         row until every pending root has found a parent).
+ *   stats                 may be NULL; not allowed with opt->async.  reached
+ *                         and reached_degree_sum are summed over the roots,
+ *                         num_layers is the deepest root's, layer_launches
+ *                         counts push and pull kernels, device_us sums the
+ *                         groups.  `layers` describes the first group: n_f and
+ *                         m_f count the union of its roots' frontiers, m_u the
+ *                         degree sum of vertices some root has not reached,
+ *                         v_u is -1.
+ * Errors: BFS_E_INVALID, BFS_E_NOMEM, BFS_E_DEVICE.
+ */
+int bfs_run_batch(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t *level_out,
+                  int32_t *parent_out, const bfs_options *opt, bfs_stats *stats);
 
 /* Wait for all work enqueued on `stream` for this graph and report any
  * failure of asynchronous runs (BFS_E_DEVICE). */

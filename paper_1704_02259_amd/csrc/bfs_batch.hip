@@ -1,0 +1,535 @@
+// gfx950 kernels of the batched multi-source BFS: up to 64 roots traverse one
+// graph together, lane b of a per-vertex uint64 mask standing for root b, so
+// a row read once serves every root (adjacency reads are shared).  Outputs
+// equal 64 single-root runs: level[b][v] and the canonical (smallest-id)
+// parent of v in root b's tree.
+//
+// Per layer d two kernels run:
+//   push (top-down layers only, Algorithm 1 on masks): every vertex u in any
+//        lane's frontier ORs fm_front[u] & ~vis[v] into fm_next[v] for each
+//        neighbour v -- one pass over u's row for all 64 roots;
+//   pull (every layer, Algorithm 2 on masks): each vertex v with lanes still
+//        to resolve -- all unvisited lanes (bottom-up) or the lanes push
+//        discovered (top-down) -- scans its ascending row; the first u whose
+//        frontier mask holds lane b is lane b's parent.  The first occurrence
+//        of every lane inside a 64-entry chunk comes from an exclusive OR-scan
+//        across the lanes.  The owner of v then stores next[v] and vis[v].
+// Every block of both kernels reads the layer's counters and takes the same
+// direction decision (Algorithm 3 on counts summed over the lanes), as in the
+// single-root path.
+#include "bfs_device.h"
+#include "bfs_wave.h"
+
+namespace hybfs {
+
+static __device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+    return x;
+}
+
+// OR of x over the lanes below this one (all lanes active).
+static __device__ __forceinline__ unsigned long long wave_excl_or(unsigned long long x)
+{
+    const int lane = __lane_id();
+    unsigned long long incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(incl, (unsigned)o);
+        if (lane >= o) incl |= y;
+    }
+    const unsigned long long ex = __shfl_up(incl, 1u);
+    return lane == 0 ? 0ull : ex;
+}
+
+// Direction from counts summed over the lanes; the table rule needs per-lane
+// vertex counts and is taken as the edge rule here.
+static __device__ __forceinline__ int bdecide(const BParams &P, int cur, long long u_nf, long long u_mf,
+                                              long long m_u)
+{
+    if (P.rule == RULE_TOPDOWN) return DIR_TD;
+    if (P.rule == RULE_BOTTOMUP) return DIR_BU;
+    if (cur == DIR_TD && u_mf * P.alpha > m_u) return DIR_BU;
+    if (cur == DIR_BU && u_nf * P.beta < P.n) return DIR_TD;
+    return cur;
+}
+
+// Lane b of `bits`: v's parent in root b's tree is u, at level d+1.
+static __device__ __forceinline__ void emit(const BParams &P, long long v, int u, int d,
+                                            unsigned long long bits)
+{
+    while (bits) {
+        const int b = __ffsll((long long)bits) - 1;
+        bits &= bits - 1;
+        P.level[(long long)b * P.n + v] = d + 1;
+        P.parent[(long long)b * P.n + v] = u;
+    }
+}
+
+struct BView {
+    int done;
+    int pad;
+    int *level;
+    int *parent;
+    BLayerState S;
+    long long c[6];
+};
+
+// Thread 0 reads the control data once per block; `coherent` reads the
+// counters at the device-coherent level (needed in the single-block finisher,
+// whose own atomics may be newer than its L1).
+static __device__ void load_view(const BParams &P, int parity, int d_hint, BView *view, bool coherent)
+{
+    if (threadIdx.x == 0) {
+        BCtrl *C = P.ctrl;
+        view->done = C->done;
+        view->level = C->level;
+        view->parent = C->parent;
+        view->S = C->st[parity];
+        BSlot &sl = C->slot[view->S.d % kSlots];
+        for (int j = 0; j < 6; ++j) {
+            long long a = 0;
+            for (int k = 0; k < kSub; ++k) a += (long long)(coherent ? ld_relaxed(&sl.c[k][j]) : sl.c[k][j]);
+            view->c[j] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Push (top-down) for layer d.  Returns false when the batch is complete.
+static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, long long gwave,
+                                  long long nwaves, bool leader, BView *view, bool coherent)
+{
+    load_view(Pin, parity, d_hint, view, coherent);
+    if (view->done) return false;
+    BParams P = Pin;
+    P.level = view->level;
+    P.parent = view->parent;
+    BCtrl *C = P.ctrl;
+    const int d = view->S.d;
+    if (d_hint >= 0 && d != d_hint) {
+        if (leader) atomicOr((unsigned *)&C->status, 16u);
+        return false;
+    }
+    const long long pairs = view->c[0];
+    const long long m_u = view->S.m_u - view->c[3];
+    if (pairs == 0 || d > P.n) {
+        if (leader) {
+            C->nlayers = d;
+            C->pairs = view->S.pairs;
+            C->pairs_deg = view->S.pairs_deg;
+            C->done = d > P.n ? 2 : 1;
+        }
+        return false;
+    }
+    if (bdecide(P, view->S.dir_prev, view->c[1], view->c[2], m_u) != DIR_TD) return true;
+
+    const int lane = __lane_id();
+    const unsigned long long *front = P.fm + (long long)(d % 3) * P.n;
+    unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
+    const unsigned long long *ufront = P.ubm + (long long)(d % 3) * P.W;
+    const int G = P.wpg_td;
+    for (long long base = gwave * G; base < P.W; base += nwaves * G) {
+        const long long myw = base + lane;
+        const unsigned long long fwl = (lane < G && myw < P.W) ? ufront[myw] : 0ull;
+        const int cnt = __popcll(fwl);
+        const int cincl = wave_incl_scan32(cnt);
+        const int cex = cincl - cnt;
+        const int V = __builtin_amdgcn_readlane(cincl, 63);
+        for (int vr = 0; vr < V; vr += 64) {
+            const int vi = vr + lane;
+            const bool vok = vi < V;
+            const int l = lane_search(cex, vok ? vi : 0);
+            const unsigned long long fw = (unsigned long long)__shfl((long long)fwl, l);
+            const int kth = vi - __shfl(cex, l);
+            int u = 0, dl = 0;
+            long long sl = 0;
+            unsigned long long fu = 0;
+            if (vok) {
+                u = (int)(((base + l) << 6) + select_bit(fw, kth));
+                if ((unsigned)u >= (unsigned)P.n) {
+                    atomicOr((unsigned *)&C->status, 8u);
+                    u = 0;
+                }
+                dl = P.deg[u];
+                sl = P.off[u];
+                fu = front[u];
+                if (dl > P.hub_deg) dl = 0;      // through the hub table below
+            }
+            const int incl = wave_incl_scan32(dl);
+            const int ex = incl - dl;
+            const int E = __builtin_amdgcn_readlane(incl, 63);
+            for (int r0 = 0; r0 < E; r0 += 64) {
+                const int idx = r0 + lane;
+                const int lo = lane_search(ex, idx < E ? idx : 0);
+                const long long j = __shfl(sl, lo) + (idx - __shfl(ex, lo));
+                const unsigned long long fq = (unsigned long long)__shfl((long long)fu, lo);
+                if (idx < E) {
+                    if ((unsigned long long)j >= (unsigned long long)P.nnz) {
+                        atomicOr((unsigned *)&C->status, 4u);
+                    } else {
+                        const int v = P.col[j];
+                        const unsigned long long m = fq & ~P.vis[v];
+                        if (m) atomicOr(&next[v], m);
+                    }
+                }
+            }
+        }
+    }
+    if (view->c[4] > 0) {
+        const long long CH = 1ll << P.hub_log2;
+        for (long long b0 = gwave; b0 < P.n_hub; b0 += nwaves * 64) {
+            const long long idx = b0 + (long long)lane * nwaves;
+            Item it{-1, 0};
+            if (idx < P.n_hub) it = P.hub[idx];
+            const bool hit = it.u >= 0 && test_bit(ufront, it.u);
+            unsigned long long m = __ballot(hit);
+            while (m) {
+                const int kk = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const int uh = __builtin_amdgcn_readlane(it.u, kk);
+                const int ch = __builtin_amdgcn_readlane(it.chunk, kk);
+                const unsigned long long fu = front[uh];
+                const long long s = P.off[uh] + ((long long)ch << P.hub_log2);
+                const long long e = min(s + CH, P.off[uh + 1]);
+                for (long long j = s + lane; j < e; j += 64) {
+                    const int v = P.col[j];
+                    const unsigned long long mm = fu & ~P.vis[v];
+                    if (mm) atomicOr(&next[v], mm);
+                }
+            }
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Pull for layer d: resolve parents, store next and vis, count F_{d+1}.
+static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, long long gwave,
+                                  long long nwaves, long long gt, long long nt, bool leader,
+                                  BView *view, unsigned long long *s_red, int nwaves_block,
+                                  bool coherent)
+{
+    load_view(Pin, parity, d_hint, view, coherent);
+    if (view->done) return;
+    BParams P = Pin;
+    P.level = view->level;
+    P.parent = view->parent;
+    BCtrl *C = P.ctrl;
+    const int d = view->S.d;
+    if (d_hint >= 0 && d != d_hint) return;
+    // the same decision as the push kernel of this layer, from the same data
+    const long long m_u = view->S.m_u - view->c[3];
+    const int cur = bdecide(P, view->S.dir_prev, view->c[1], view->c[2], m_u);
+    const int lane = __lane_id();
+    const unsigned long long *front = P.fm + (long long)(d % 3) * P.n;
+    unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
+    unsigned long long *spare = P.fm + (long long)((d + 2) % 3) * P.n;
+    unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
+    unsigned long long *uspare = P.ubm + (long long)((d + 2) % 3) * P.W;
+    unsigned long long cnt[6] = {0, 0, 0, 0, 0, 0};
+    const int G = P.wpg;
+    for (long long base = gwave * G; base < P.W; base += nwaves * G) {
+        for (int wi = 0; wi < G; ++wi) {
+            const long long w = base + wi;
+            if (w >= P.W) break;
+            const long long v = (w << 6) + lane;
+            const bool inr = v < P.n;
+            unsigned long long vm = P.active, need = 0;
+            if (inr) {
+                vm = P.vis[v];
+                need = cur == DIR_TD ? next[v] : (P.active & ~vm);
+            }
+            if (!__ballot(need != 0)) continue;
+            const int dg = need ? P.deg[v] : 0;
+            long long s = 0;
+            if (need && dg > 0) s = P.off[v];
+            unsigned long long found = 0;
+            // short rows: one lane scans its own row
+            if (need && dg > 0 && dg <= 32) {
+                unsigned long long rem = need;
+                for (long long j = s; j < s + dg; ++j) {
+                    const int u = P.col[j];
+                    const unsigned long long f = front[u] & rem;
+                    if (f) {
+                        emit(P, v, u, d, f);
+                        found |= f;
+                        rem &= ~f;
+                        if (!rem) break;
+                    }
+                }
+            }
+            // long rows: the whole wavefront, 64 entries per step
+            unsigned long long longm = __ballot(need != 0 && dg > 32);
+            while (longm) {
+                const int k = __ffsll((long long)longm) - 1;
+                longm &= longm - 1;
+                const long long vk = bcast64(v, k);
+                const long long sk = bcast64(s, k);
+                const long long ek = sk + __builtin_amdgcn_readlane(dg, k);
+                unsigned long long remk = bcast_u64(need, k);
+                unsigned long long foundk = 0;
+                for (long long b = sk; b < ek && remk; b += 64) {
+                    const long long j = b + lane;
+                    int u = 0;
+                    unsigned long long f = 0;
+                    if (j < ek) {
+                        u = P.col[j];
+                        f = front[u] & remk;
+                    }
+                    const unsigned long long newb = f & ~wave_excl_or(f);
+                    if (newb) emit(P, vk, u, d, newb);
+                    const unsigned long long all = wave_or_u64(f);
+                    remk &= ~all;
+                    foundk |= all;
+                }
+                if (lane == k) found |= foundk;
+            }
+            if (found) {
+                if (cur != DIR_TD) next[v] = found;     // push already stored it
+                P.vis[v] = vm | found;
+                const unsigned long long np = (unsigned long long)__popcll(found);
+                cnt[0] += np;
+                cnt[5] += np * (unsigned long long)dg;
+                cnt[1] += 1;
+                cnt[2] += (unsigned long long)dg;
+                cnt[3] += ((vm | found) == P.active) ? (unsigned long long)dg : 0ull;
+                cnt[4] += dg > P.hub_deg;
+            }
+            // every lane pushed here has a frontier neighbour in its row
+            if (cur == DIR_TD && found != need) atomicOr((unsigned *)&C->status, 32u);
+            const unsigned long long um = __ballot(found != 0);
+            if (lane == 0 && um) unext[w] = um;
+        }
+    }
+    // clear the buffers that become `next` in layer d+1
+    for (long long i = gt; i < P.n; i += nt) spare[i] = 0ull;
+    for (long long i = gt; i < P.W; i += nt) uspare[i] = 0ull;
+    if (leader) {
+        BLayerState Nx = view->S;
+        Nx.d = d + 1;
+        Nx.dir_prev = cur;
+        Nx.m_u = m_u;
+        Nx.pairs = view->S.pairs + view->c[0];
+        Nx.pairs_deg = view->S.pairs_deg + view->c[5];
+        C->st[parity ^ 1] = Nx;
+        C->parity = parity ^ 1;
+        BSlot *Z = &C->slot[(d + 2) % kSlots];
+        for (int k = 0; k < kSub; ++k)
+            for (int j = 0; j < 6; ++j) Z->c[k][j] = 0;
+        if (d < P.trace_cap) {
+            LayerRec r;
+            r.dir = cur;
+            r.pad = 0;
+            r.n_f = view->c[1];
+            r.m_f = view->c[2];
+            r.m_u = m_u;
+            r.v_u = -1;
+            r.t = 0;
+            P.trace[d] = r;
+        }
+    }
+    // counters of F_{d+1}
+    const int wib = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const unsigned long long t = wave_sum_u64(cnt[j]);
+        if (lane == 0) s_red[6 * wib + j] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BSlot &sl = C->slot[(d + 1) % kSlots];
+        unsigned long long *sub = sl.c[blockIdx.x % kSub];
+        for (int j = 0; j < 6; ++j) {
+            unsigned long long a = 0;
+            for (int i = 0; i < nwaves_block; ++i) a += s_red[6 * i + j];
+            if (a) atomicAdd(&sub[j], a);
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P)
+{
+    const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long nt = (long long)gridDim.x * kBlock;
+    const long long total = (long long)P.k * P.n;
+    const bool vec = ((((unsigned long long)P.level) | ((unsigned long long)P.parent)) & 15ull) == 0;
+    const long long n4 = vec ? (total >> 2) : 0;
+    const int4 m1 = make_int4(-1, -1, -1, -1);
+    for (long long i = gt; i < n4; i += nt) {
+        ((int4 *)P.level)[i] = m1;
+        ((int4 *)P.parent)[i] = m1;
+    }
+    for (long long i = (n4 << 2) + gt; i < total; i += nt) {
+        P.level[i] = -1;
+        P.parent[i] = -1;
+    }
+    for (long long v = gt; v < P.n; v += nt) {
+        // vertices without edges count as visited in every lane: they are
+        // never reached (a root among them is seeded separately)
+        P.vis[v] = test_bit(P.iso, (int)v) ? P.active : 0ull;
+        P.fm[v] = 0ull;
+        P.fm[P.n + v] = 0ull;
+    }
+    for (long long w = gt; w < P.W; w += nt) {
+        P.ubm[w] = 0ull;
+        P.ubm[P.W + w] = 0ull;
+    }
+    if (gt == 0) {
+        BCtrl *C = P.ctrl;
+        C->done = 0;
+        C->nlayers = 0;
+        C->parity = 0;
+        C->status = 0;
+        C->level = P.level;
+        C->parent = P.parent;
+        C->pairs = 0;
+        C->pairs_deg = 0;
+        BLayerState S;
+        S.d = 0;
+        S.dir_prev = DIR_TD;
+        S.m_u = P.nnz;
+        S.pairs = 0;
+        S.pairs_deg = 0;
+        for (int i = 0; i < 4; ++i) S.pad[i] = 0;
+        C->st[0] = S;
+        C->st[1] = S;
+        for (int k = 0; k < kSlots; ++k)
+            for (int j = 0; j < kSub; ++j)
+                for (int c = 0; c < 8; ++c) C->slot[k].c[j][c] = 0;
+    }
+}
+
+// One wavefront: the roots' entries, masks and the counters of F_0.
+__global__ void __launch_bounds__(64) bfs_batch_seed_kernel(BParams P, RootSet R)
+{
+    const int lane = threadIdx.x;
+    const bool on = lane < P.k;
+    const int r = on ? R.r[lane] : -1;
+    unsigned long long mask = 0;
+    bool first = on;
+    for (int b = 0; b < kLanes; ++b) {
+        const int rb = __shfl(r, b);
+        if (on && b < P.k && rb == r) {
+            mask |= 1ull << b;
+            if (b < lane) first = false;
+        }
+    }
+    unsigned long long c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+    if (on) {
+        P.level[(long long)lane * P.n + r] = 0;
+        P.parent[(long long)lane * P.n + r] = r;
+        c5 = (unsigned long long)P.deg[r];
+    }
+    if (first) {
+        const unsigned long long vm = test_bit(P.iso, r) ? P.active : 0ull;
+        P.fm[r] = mask;
+        P.vis[r] = vm | mask;
+        atomicOr(&P.ubm[r >> 6], 1ull << (r & 63));
+        const int dg = P.deg[r];
+        c1 = 1;
+        c2 = (unsigned long long)dg;
+        c3 = (mask == P.active && vm != P.active) ? (unsigned long long)dg : 0ull;
+        c4 = dg > P.hub_deg;
+    }
+    c1 = wave_sum_u64(c1);
+    c2 = wave_sum_u64(c2);
+    c3 = wave_sum_u64(c3);
+    c4 = wave_sum_u64(c4);
+    c5 = wave_sum_u64(c5);
+    if (lane == 0) {
+        BSlot &sl = P.ctrl->slot[0];
+        sl.c[0][0] = (unsigned long long)P.k;
+        sl.c[0][1] = c1;
+        sl.c[0][2] = c2;
+        sl.c[0][3] = c3;
+        sl.c[0][4] = c4;
+        sl.c[0][5] = c5;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) bfs_batch_push_kernel(BParams P, int layer)
+{
+    __shared__ BView view;
+    const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
+    batch_push(P, layer & 1, layer, gwave, nwaves, blockIdx.x == 0 && threadIdx.x == 0, &view, false);
+}
+
+__global__ void __launch_bounds__(kBlock) bfs_batch_pull_kernel(BParams P, int layer)
+{
+    __shared__ BView view;
+    __shared__ unsigned long long s_red[6 * kWavesPerBlock];
+    const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
+    const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long nt = (long long)gridDim.x * kBlock;
+    batch_pull(P, layer & 1, layer, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, &view,
+               s_red, kWavesPerBlock, false);
+}
+
+// One block runs whatever layers remain, with block barriers between phases.
+__global__ void __launch_bounds__(kFinishBlock) bfs_batch_finish_kernel(BParams P)
+{
+    __shared__ BView view;
+    __shared__ unsigned long long s_red[6 * (kFinishBlock / 64)];
+    __shared__ int s_parity;
+    const long long gwave = threadIdx.x >> 6;
+    const long long nwaves = kFinishBlock / 64;
+    for (;;) {
+        if (threadIdx.x == 0) s_parity = P.ctrl->parity;
+        __syncthreads();
+        const int parity = s_parity;
+        __syncthreads();
+        if (!batch_push(P, parity, -1, gwave, nwaves, threadIdx.x == 0, &view, true)) break;
+        __syncthreads();
+        batch_pull(P, parity, -1, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, &view, s_red,
+                   kFinishBlock / 64, true);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch_init(const BParams &p, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_batch_init_kernel, dim3(grid), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_seed(const BParams &p, const RootSet &roots, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_batch_seed_kernel, dim3(1), dim3(64), 0, s, p, roots);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_push(const BParams &p, int layer, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_batch_push_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pull(const BParams &p, int layer, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_batch_pull_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finish(const BParams &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_batch_finish_kernel, dim3(1), dim3(kFinishBlock), 0, s, p);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu()
+{
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, bfs_batch_pull_kernel, kBlock, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, bfs_batch_push_kernel, kBlock, 0) != hipSuccess)
+        return -1;
+    return a < b ? a : b;
+}
+
+}  // namespace hybfs

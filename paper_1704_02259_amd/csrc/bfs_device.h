@@ -97,6 +97,79 @@ struct Params {
     int pad1;
 };
 
+// ---------------------------------------------------------------------------
+// Batched multi-source traversal: lane b of every uint64 mask is root b.
+constexpr int kLanes = 64;
+
+// Counters of one batched frontier F_d (per sub-counter line):
+//   c[k][0] (root, vertex) pairs in F_d          c[k][1] vertices in any lane's F_d
+//   c[k][2] degree sum of those vertices         c[k][3] degree sum of vertices that
+//   c[k][4] of them above hub_deg                        became visited in every lane
+//   c[k][5] degree sum over the pairs
+struct BSlot {
+    unsigned long long c[kSub][8];
+};
+
+struct BLayerState {
+    int d;
+    int dir_prev;
+    long long m_u;                   // degree sum of vertices not visited in every lane
+    long long pairs;                 // (root, vertex) pairs in layers 0..d-1
+    long long pairs_deg;             // their degree sum
+    long long pad[4];
+};
+
+struct BCtrl {
+    int done;
+    int nlayers;
+    int parity;
+    int status;
+    int *level;
+    int *parent;
+    long long pairs;
+    long long pairs_deg;
+    long long pad[4];
+    BLayerState st[2];
+    BSlot slot[kSlots];
+};
+
+struct RootSet {
+    int r[kLanes];
+};
+
+struct BParams {
+    long long n, nnz, W;
+    const long long *off;
+    const int *col;
+    const int *deg;
+    const unsigned long long *iso;
+    const Item *hub;
+    long long n_hub;
+    int hub_log2;
+    int hub_deg;
+    int k;                               // lanes in use (1..64)
+    int rule;
+    unsigned long long active;           // bit b set for b < k
+    unsigned long long *vis;             // [n] lanes that reached v in a finished layer
+    unsigned long long *fm;              // [3n] rotating lane masks: frontier / next / spare
+    unsigned long long *ubm;             // [3W] rotating bitmaps: vertex has a nonzero mask
+    int *level, *parent;                 // outputs [k * n], root-major
+    BCtrl *ctrl;
+    LayerRec *trace;
+    int trace_cap;
+    int wpg;                             // pull: bitmap words per wavefront task
+    int wpg_td;                          // push: bitmap words per wavefront task
+    int pad;
+    long long alpha, beta;
+};
+
+hipError_t launch_batch_init(const BParams &p, int grid, hipStream_t s);
+hipError_t launch_batch_seed(const BParams &p, const RootSet &roots, hipStream_t s);
+hipError_t launch_batch_push(const BParams &p, int layer, int grid, hipStream_t s);
+hipError_t launch_batch_pull(const BParams &p, int layer, int grid, hipStream_t s);
+hipError_t launch_batch_finish(const BParams &p, hipStream_t s);
+int batch_blocks_per_cu();
+
 // Launchers (defined in bfs_kernels.hip).
 hipError_t launch_init(const Params &p, int grid, hipStream_t s);
 hipError_t launch_layer(const Params &p, int layer, int grid, hipStream_t s);

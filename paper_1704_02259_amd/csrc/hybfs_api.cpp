@@ -199,7 +199,7 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     P.level = lvl;
     P.parent = par;
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
-    const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->typical_layers.load();
+    const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
     hipError_t e;
     if (profile) {
         while ((int)w->layer_ev.size() < 2 * L) {
@@ -229,7 +229,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     Params P;
     fill_params(g, w, opt, &P);
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
-    const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->typical_layers.load();
+    const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
     char key[160];
     snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k, P.wpg,
              P.wpg_td, grid, L);
@@ -298,13 +298,13 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
 // Adaptive layer count: the deepest of the last 16 traversals.  A traversal of
 // that depth ends in the single-block finisher, which only has to see the
 // empty frontier; deeper ones are finished there.
-static void note_depth(Graph *g, int nlayers)
+void DepthTracker::note(int nlayers)
 {
-    const unsigned pos = g->recent_pos.fetch_add(1) % 16;
-    g->recent_depth[pos].store(nlayers);
+    const unsigned p = pos.fetch_add(1) % 16;
+    recent[p].store(nlayers);
     int mx = 0;
-    for (int i = 0; i < 16; ++i) mx = std::max(mx, g->recent_depth[i].load());
-    g->typical_layers.store(std::min(std::max(mx, 2), 64));
+    for (int i = 0; i < 16; ++i) mx = std::max(mx, recent[i].load());
+    typical.store(std::min(std::max(mx, 2), 64));
 }
 
 }  // namespace hybfs
@@ -482,7 +482,13 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     int wpg = 1;
     while (wpg < 64 && (g->W + wpg - 1) / wpg > 2 * resident_waves) wpg <<= 1;
     g->wpg_default = wpg;
-    for (int i = 0; i < 16; ++i) g->recent_depth[i].store(9);
+    for (int i = 0; i < 16; ++i) {
+        g->depth.recent[i].store(9);
+        g->batch_depth.recent[i].store(9);
+    }
+    const int bper_cu = batch_blocks_per_cu();
+    if (bper_cu < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
+    g->batch_grid = std::min(bper_cu, 4) * cus;
     *out = reinterpret_cast<bfs_graph_t>(g.release());
     return BFS_OK;
 }
@@ -495,6 +501,8 @@ int bfs_graph_destroy(bfs_graph_t gh)
     hipDeviceSynchronize();
     for (auto &kv : g->ws) kv.second.reset();
     g->ws.clear();
+    for (auto &kv : g->bws) kv.second.reset();
+    g->bws.clear();
     if (g->d_off) hipFree(g->d_off);
     if (g->d_col) hipFree(g->d_col);
     if (g->d_iso) hipFree(g->d_iso);
@@ -524,7 +532,8 @@ int bfs_graph_info_get(bfs_graph_t gh, bfs_graph_info *info)
     info->chunk_edges = 1 << kChunkLog2;
     info->hub_degree = g->hub_deg;
     info->hub_chunks = g->n_hub;
-    info->typical_layers = g->typical_layers.load();
+    info->typical_layers = g->depth.typical.load();
+    info->batch_workspace_bytes = (int64_t)batch_workspace_bytes(g->n, g->W);
     return BFS_OK;
 }
 
@@ -592,7 +601,7 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
         return set_error(BFS_E_DEVICE, "traversal failed a device-side check (done %d, status %d)",
                          c.done, c.status);
     }
-    note_depth(g, c.nlayers);
+    g->depth.note(c.nlayers);
     if (stats) {
         stats->num_layers = c.nlayers;
         stats->reached = c.reached;

@@ -45,6 +45,38 @@ struct Workspace {
     ~Workspace();
 };
 
+// Per-stream scratch of a batched traversal (up to 64 roots per group).
+struct BatchWorkspace {
+    std::mutex mu;
+    void *dbuf = nullptr;
+    size_t bytes = 0;
+    unsigned long long *vis = nullptr;   // [n]
+    unsigned long long *fm = nullptr;    // [3n]
+    unsigned long long *ubm = nullptr;   // [3W]
+    BCtrl *ctrl = nullptr;
+    LayerRec *trace = nullptr;
+    int *out_tmp = nullptr;              // host-output staging: level + parent of one group
+    long long out_tmp_elems = 0;
+    BCtrl *h_ctrl = nullptr;             // pinned
+    LayerRec *h_trace = nullptr;         // pinned
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<hipEvent_t> layer_ev;
+    ~BatchWorkspace();
+};
+
+// Launch depth of the layered kernels: the deepest of the last 16 traversals,
+// clamped to [2, 64].  Deeper traversals are completed by the finisher.
+struct DepthTracker {
+    std::atomic<int> typical{10};
+    std::atomic<int> recent[16];
+    std::atomic<unsigned> pos{0};
+    DepthTracker()
+    {
+        for (auto &r : recent) r.store(0);
+    }
+    void note(int nlayers);
+};
+
 struct Graph {
     int dev = 0;
     long long n = 0, nnz = 0, W = 0;
@@ -62,11 +94,12 @@ struct Graph {
     int blocks_per_cu = 0;
     int grid_default = 0;
     int wpg_default = 1;
-    std::atomic<int> typical_layers{10};
-    std::atomic<int> recent_depth[16];   // depths of the last traversals (ring)
-    std::atomic<unsigned> recent_pos{0};
+    DepthTracker depth;                  // single-root traversals
+    DepthTracker batch_depth;            // batched traversals
+    int batch_grid = 0;
     std::mutex mu;
     std::map<void *, std::unique_ptr<Workspace>> ws;
+    std::map<void *, std::unique_ptr<BatchWorkspace>> bws;
 };
 
 int set_error(int code, const char *fmt, ...);
@@ -77,6 +110,7 @@ int validate_options(const bfs_options &o);
 int check_csr(int64_t n, int64_t nnz, const int64_t *off, const int32_t *col, bool need_sorted,
               bool check_symmetry);
 int get_workspace(Graph *g, void *stream, Workspace **out);
+size_t batch_workspace_bytes(long long n, long long W);
 void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P);
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
                       hipStream_t s, int *layers_enqueued, bool profile);

@@ -61,7 +61,8 @@ class bfs_graph_info(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_int64), ("grid_blocks", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("slab_k", ctypes.c_int32),
                 ("chunk_edges", ctypes.c_int32), ("typical_layers", ctypes.c_int32),
-                ("hub_degree", ctypes.c_int32), ("hub_chunks", ctypes.c_int64)]
+                ("hub_degree", ctypes.c_int32), ("hub_chunks", ctypes.c_int64),
+                ("batch_workspace_bytes", ctypes.c_int64)]
 
 
 class HybfsError(RuntimeError):
@@ -91,6 +92,8 @@ def load():
         "bfs_graph_info_get": (ctypes.c_int, [vp, ctypes.POINTER(bfs_graph_info)]),
         "bfs_run": (ctypes.c_int, [vp, i32, vp, vp, ctypes.POINTER(bfs_options),
                                    ctypes.POINTER(bfs_stats)]),
+        "bfs_run_batch": (ctypes.c_int, [vp, vp, i32, vp, vp, ctypes.POINTER(bfs_options),
+                                         ctypes.POINTER(bfs_stats)]),
         "bfs_graph_sync": (ctypes.c_int, [vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -143,6 +146,13 @@ def bfs_run(g: int, root: int, level_out: int, parent_out: int, opt: bfs_options
     _check(load().bfs_run(g, root, level_out, parent_out,
                           ctypes.byref(opt) if opt is not None else None,
                           ctypes.byref(stats) if stats is not None else None))
+
+
+def bfs_run_batch(g: int, roots: int, k: int, level_out: int, parent_out: int,
+                  opt: bfs_options | None = None, stats: bfs_stats | None = None):
+    _check(load().bfs_run_batch(g, roots, k, level_out, parent_out,
+                                ctypes.byref(opt) if opt is not None else None,
+                                ctypes.byref(stats) if stats is not None else None))
 
 
 def bfs_graph_sync(g: int, stream: int | None = None):
@@ -216,6 +226,38 @@ class Graph:
         if stats:
             st, arr = make_stats(4096)
         bfs_run(self.handle, int(root), lp, pp, opt, st)
+        if stats:
+            return level, parent, {"num_layers": st.num_layers, "reached": st.reached,
+                                   "reached_degree_sum": st.reached_degree_sum,
+                                   "device_us": st.device_us, "layer_launches": st.layer_launches,
+                                   "layer_kernel_us": st.layer_kernel_us,
+                                   "layers": stats_layers(st, arr)}
+        return level, parent
+
+    def run_batch(self, roots, level=None, parent=None, stream=None, stats: bool = False, **kw):
+        """Batched BFS from every root in `roots` (bfs_run_batch).  Outputs are
+        root-major k x n: torch CUDA tensors stay on the device, otherwise numpy
+        arrays of shape (k, n) are returned."""
+        import torch
+        r = np.ascontiguousarray(np.asarray(roots, dtype=np.int32).reshape(-1))
+        k = len(r)
+        dev_out = level is not None
+        if level is None:
+            level = np.empty((k, self.n), dtype=np.int32)
+            parent = np.empty((k, self.n), dtype=np.int32)
+            lp, pp = level.ctypes.data, parent.ctypes.data
+        else:
+            assert level.dtype == torch.int32 and parent.dtype == torch.int32
+            assert level.is_cuda and parent.is_cuda and level.is_contiguous() and parent.is_contiguous()
+            assert level.numel() >= k * self.n and parent.numel() >= k * self.n
+            lp, pp = level.data_ptr(), parent.data_ptr()
+            if stream is None:
+                stream = torch.cuda.current_stream().cuda_stream
+        opt = bfs_options_init(out_on_device=1 if dev_out else 0, stream=stream, **kw)
+        st = arr = None
+        if stats:
+            st, arr = make_stats(4096)
+        bfs_run_batch(self.handle, r.ctypes.data if k else None, k, lp, pp, opt, st)
         if stats:
             return level, parent, {"num_layers": st.num_layers, "reached": st.reached,
                                    "reached_degree_sum": st.reached_degree_sum,

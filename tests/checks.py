@@ -167,3 +167,22 @@ def hypercube_expected(dim: int, r: int):
             b = (x & -x).bit_length() - 1
         parent[v] = v ^ (1 << b)
     return level, parent
+
+
+def batch_union_replay(g, levels) -> dict:
+    """Per-layer counters a batched traversal decides on, from the roots' level
+    arrays (k x n): n_f and m_f over the union of the roots' frontiers F_d, and
+    m_u = degree sum of the vertices that are not yet at a level <= d in every
+    root's traversal."""
+    lv = np.asarray(levels, dtype=np.int64).reshape(-1, g.n)
+    deg = np.diff(np.asarray(g.off, dtype=np.int64))
+    L = int(lv.max()) + 1 if lv.size else 0
+    unreached = np.where(lv < 0, np.iinfo(np.int64).max, lv)
+    done_at = unreached.max(axis=0)        # layer after which v is visited in every root
+    out = {"n_f": [], "m_f": [], "m_u": []}
+    for d in range(L):
+        in_f = (lv == d).any(axis=0)
+        out["n_f"].append(int(in_f.sum()))
+        out["m_f"].append(int(deg[in_f].sum()))
+        out["m_u"].append(int(deg[done_at > d].sum()))
+    return {k: np.array(v, dtype=np.int64) for k, v in out.items()}

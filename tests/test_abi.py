@@ -28,8 +28,8 @@ def declared_functions():
 
 def test_header_declares_entry_points():
     names = declared_functions()
-    for required in ("bfs_graph_create", "bfs_graph_destroy", "bfs_run", "bfs_last_error",
-                     "bfs_options_init"):
+    for required in ("bfs_graph_create", "bfs_graph_destroy", "bfs_run", "bfs_run_batch",
+                     "bfs_last_error", "bfs_options_init"):
         assert required in names
 
 
@@ -81,6 +81,12 @@ def test_graph_create_rejects_bad_csr_on_host(lib):
 def test_run_rejects_null_graph(lib):
     z = np.zeros(4, np.int32)
     rc = lib.bfs_run(None, 0, z.ctypes.data, z.ctypes.data, None, None)
+    assert rc == -1 and "graph" in lib.bfs_last_error().decode()
+
+
+def test_run_batch_rejects_null_graph(lib):
+    z = np.zeros(4, np.int32)
+    rc = lib.bfs_run_batch(None, z.ctypes.data, 1, z.ctypes.data, z.ctypes.data, None, None)
     assert rc == -1 and "graph" in lib.bfs_last_error().decode()
 
 
