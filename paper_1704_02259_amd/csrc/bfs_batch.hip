@@ -6,17 +6,16 @@
 //
 // Per layer d two kernels run:
 //   push (top-down layers only, Algorithm 1 on masks): every vertex u in any
-//        lane's frontier ORs fm_front[u] & ~vis[v] into fm_next[v] for each
-//        neighbour v -- one pass over u's row for all 64 roots;
-//   pull (every layer, Algorithm 2 on masks): each vertex v with lanes still
-//        to resolve -- all unvisited lanes (bottom-up) or the lanes push
-//        discovered (top-down) -- scans its ascending row; the first u whose
-//        frontier mask holds lane b is lane b's parent.  The first occurrence
-//        of every lane inside a 64-entry chunk comes from an exclusive OR-scan
-//        across the lanes.  The owner of v then stores next[v] and vis[v].
+//        lane's frontier sends fm_front[u] & ~vis[v] to each neighbour v --
+//        one pass over u's row for all 64 roots; per lane, the parent of v is
+//        the smallest such u (an unsigned atomic minimum);
+//   pull (every layer): after a push, the vertices the push marked are folded
+//        into vis and counted; in a bottom-up layer (Algorithm 2 on masks)
+//        each vertex with lanes still unvisited scans its ascending row and
+//        the first u whose frontier mask holds lane b is lane b's parent.
 // Every block of both kernels reads the layer's counters and takes the same
-// direction decision (Algorithm 3 on counts summed over the lanes), as in the
-// single-root path.
+// direction decision (Algorithm 3 on counts over the union of the lanes'
+// frontiers), as in the single-root path.
 #include "bfs_device.h"
 #include "bfs_wave.h"
 
@@ -55,15 +54,99 @@ static __device__ __forceinline__ int bdecide(const BParams &P, int cur, long lo
     return cur;
 }
 
-// Lane b of `bits`: v's parent in root b's tree is u, at level d+1.
-static __device__ __forceinline__ void emit(const BParams &P, long long v, int u, int d,
-                                            unsigned long long bits)
+// Lane b of `bits`: v's parent in root b's tree is u.  (The levels of a
+// bottom-up layer are stored afterwards, per lane across a word of vertices.)
+static __device__ __forceinline__ void emit_parent(const BParams &P, long long v, int u, unsigned long long bits)
 {
     while (bits) {
         const int b = __ffsll((long long)bits) - 1;
         bits &= bits - 1;
-        P.level[(long long)b * P.n + v] = d + 1;
         P.parent[(long long)b * P.n + v] = u;
+    }
+}
+
+// Level d+1 for the lanes `found` of this lane's vertex v: one store per lane
+// b across the wavefront, so the 64 vertices of a word fill 256 contiguous
+// bytes of root b's level array.  All lanes of the wavefront must be active.
+static __device__ __forceinline__ void store_levels(const BParams &P, long long v, int d, unsigned long long found)
+{
+    unsigned long long all = wave_or_u64(found);
+    while (all) {
+        const int b = __ffsll((long long)all) - 1;
+        all &= all - 1;
+        if ((found >> b) & 1ull) P.level[(long long)b * P.n + v] = d + 1;
+    }
+}
+
+// Top-down edge u -> v for the lanes in m (u in their frontier, v not yet
+// visited by them): the lanes' parent of v is the smallest such u, taken by
+// an unsigned atomic minimum over the -1 the outputs start from; the first
+// edge to bring a lane stores its level, the first to reach v at all marks v
+// in the next frontier's bitmap.
+static __device__ __forceinline__ void td_discover(const BParams &P, unsigned long long *next,
+                                                   unsigned long long *unext, int v, int u, int d,
+                                                   unsigned long long m)
+{
+    const unsigned long long old = atomicOr(&next[v], m);
+    if (old == 0) atomicOr(&unext[v >> 6], 1ull << (v & 63));
+    const unsigned long long fresh = m & ~old;
+    while (m) {
+        const int b = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const long long i = (long long)b * P.n + v;
+        atomicMin((unsigned *)&P.parent[i], (unsigned)u);
+        if ((fresh >> b) & 1ull) P.level[i] = d + 1;
+    }
+}
+
+// Bottom-up layer, rows longer than hub_deg: each 2^hub_log2-entry chunk of
+// such a row (the hub table) is scanned by one wavefront, so a long row is
+// spread over many wavefronts.  Within its chunk a wavefront finds every
+// pending lane's first hit (exclusive OR-scan over the lanes of each 64-entry
+// step) and stops once all pending lanes have one; across chunks the
+// smallest hit wins through an unsigned atomic minimum on the parent.  The
+// chunk's lanes are ORed into next[v]; the pull kernel completes v.
+static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gwave, long long nwaves)
+{
+    const int lane = __lane_id();
+    const unsigned long long *front = P.fm + (long long)(d % 3) * P.n;
+    const unsigned long long *ufront = P.ubm + (long long)(d % 3) * P.W;
+    unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
+    unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
+    const long long CH = 1ll << P.hub_log2;
+    for (long long idx = gwave; idx < P.n_hub; idx += nwaves) {
+        const Item it = P.hub[idx];
+        const int v = it.u;
+        unsigned long long rem = P.active & ~P.vis[v];
+        if (!rem) continue;
+        const long long s = P.off[v] + ((long long)it.chunk << P.hub_log2);
+        const long long e = min(s + CH, P.off[v + 1]);
+        unsigned long long found = 0;
+        for (long long b = s; b < e && rem; b += 64) {
+            const long long j = b + lane;
+            int u = 0;
+            unsigned long long f = 0;
+            if (j < e) {
+                u = P.col[j];
+                if (test_bit(ufront, u)) f = front[u] & rem;
+            }
+            if (!__ballot(f != 0)) continue;
+            unsigned long long newb = f & ~wave_excl_or(f);
+            while (newb) {
+                const int bb = __ffsll((long long)newb) - 1;
+                newb &= newb - 1;
+                const long long i = (long long)bb * P.n + v;
+                atomicMin((unsigned *)&P.parent[i], (unsigned)u);
+                P.level[i] = d + 1;
+            }
+            const unsigned long long all = wave_or_u64(f);
+            rem &= ~all;
+            found |= all;
+        }
+        if (found && lane == 0) {
+            const unsigned long long old = atomicOr(&next[v], found);
+            if (old == 0) atomicOr(&unext[v >> 6], 1ull << (v & 63));
+        }
     }
 }
 
@@ -124,12 +207,16 @@ static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, lo
         }
         return false;
     }
-    if (bdecide(P, view->S.dir_prev, view->c[1], view->c[2], m_u) != DIR_TD) return true;
+    if (bdecide(P, view->S.dir_prev, view->c[1], view->c[2], m_u) != DIR_TD) {
+        push_bottom_up_hubs(P, d, gwave, nwaves);
+        return true;
+    }
 
     const int lane = __lane_id();
     const unsigned long long *front = P.fm + (long long)(d % 3) * P.n;
     unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
     const unsigned long long *ufront = P.ubm + (long long)(d % 3) * P.W;
+    unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
     const int G = P.wpg_td;
     for (long long base = gwave * G; base < P.W; base += nwaves * G) {
         const long long myw = base + lane;
@@ -166,13 +253,14 @@ static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, lo
                 const int lo = lane_search(ex, idx < E ? idx : 0);
                 const long long j = __shfl(sl, lo) + (idx - __shfl(ex, lo));
                 const unsigned long long fq = (unsigned long long)__shfl((long long)fu, lo);
+                const int uq = __shfl(u, lo);
                 if (idx < E) {
                     if ((unsigned long long)j >= (unsigned long long)P.nnz) {
                         atomicOr((unsigned *)&C->status, 4u);
                     } else {
                         const int v = P.col[j];
                         const unsigned long long m = fq & ~P.vis[v];
-                        if (m) atomicOr(&next[v], m);
+                        if (m) td_discover(P, next, unext, v, uq, d, m);
                     }
                 }
             }
@@ -197,7 +285,7 @@ static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, lo
                 for (long long j = s + lane; j < e; j += 64) {
                     const int v = P.col[j];
                     const unsigned long long mm = fu & ~P.vis[v];
-                    if (mm) atomicOr(&next[v], mm);
+                    if (mm) td_discover(P, next, unext, v, uh, d, mm);
                 }
             }
         }
@@ -206,11 +294,195 @@ static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, lo
 }
 
 // ---------------------------------------------------------------------------
-// Pull for layer d: resolve parents, store next and vis, count F_{d+1}.
+// Per-vertex bookkeeping once the lanes `found` reached v at level d+1.
+static __device__ __forceinline__ void account(const BParams &P, unsigned long long vm, unsigned long long found,
+                                               int dg, unsigned long long *cnt)
+{
+    const unsigned long long np = (unsigned long long)__popcll(found);
+    cnt[0] += np;
+    cnt[1] += 1;
+    cnt[2] += (unsigned long long)dg;
+    cnt[3] += ((vm | found) == P.active) ? (unsigned long long)dg : 0ull;
+    cnt[4] += dg > P.hub_deg;
+    cnt[5] += np * (unsigned long long)dg;
+}
+
+// After a top-down push: the vertices marked in unext are F_{d+1}; fold their
+// masks into vis and count them.  The marked vertices of a task of 64 words
+// are laid out over the lanes.
+static __device__ void pull_after_push(const BParams &P, const unsigned long long *next,
+                                       const unsigned long long *unext, long long gwave, long long nwaves,
+                                       unsigned long long *cnt)
+{
+    const int lane = __lane_id();
+    for (long long base = gwave * 64; base < P.W; base += nwaves * 64) {
+        const long long myw = base + lane;
+        const unsigned long long uw = myw < P.W ? unext[myw] : 0ull;
+        const int c = __popcll(uw);
+        const int cincl = wave_incl_scan32(c);
+        const int cex = cincl - c;
+        const int V = __builtin_amdgcn_readlane(cincl, 63);
+        for (int vr = 0; vr < V; vr += 64) {
+            const int vi = vr + lane;
+            const int l = lane_search(cex, vi < V ? vi : 0);
+            const unsigned long long wbits = (unsigned long long)__shfl((long long)uw, l);
+            const int kth = vi - __shfl(cex, l);
+            if (vi < V) {
+                const long long v = ((base + l) << 6) + select_bit(wbits, kth);
+                const unsigned long long found = next[v];
+                const unsigned long long vm = P.vis[v];
+                P.vis[v] = vm | found;
+                account(P, vm, found, P.deg[v], cnt);
+            }
+        }
+    }
+}
+
+// Bottom-up (Algorithm 2 on masks): every vertex with lanes still unvisited
+// scans its ascending row; the first u whose frontier mask holds lane b is
+// lane b's parent.  A neighbour's 8-byte mask is only loaded when the bitmap
+// of the union frontier (n/8 bytes, cache-resident) marks it.  Rows up to 32
+// entries are scanned by their own lane, four entries per step; rows up to
+// hub_deg by the whole wavefront, 64 entries per step, the first occurrence
+// of each lane in a step coming from an exclusive OR-scan over the lanes;
+// longer rows were scanned in chunks by the push kernel.
+// STAGED: for a word's 64 vertices the position of lane b's parent within
+// the row is kept in LDS (spos, [lane b][vertex] bytes = 4 KB per wavefront;
+// rows handled here have at most hub_deg <= 256 entries), and the parents
+// and levels are then stored per root b as 256-byte runs, instead of one
+// scattered 4-byte store per (root, vertex).
+template <bool STAGED>
+static __device__ void pull_bottom_up(const BParams &P, int d, const unsigned long long *front,
+                                      const unsigned long long *ufront, unsigned long long *next,
+                                      unsigned long long *unext, long long gwave, long long nwaves,
+                                      unsigned long long *cnt, unsigned char *spos)
+{
+    const int lane = __lane_id();
+    const int G = P.wpg;
+    for (long long base = gwave * G; base < P.W; base += nwaves * G) {
+        for (int wi = 0; wi < G; ++wi) {
+            const long long w = base + wi;
+            if (w >= P.W) break;
+            const long long v = (w << 6) + lane;
+            unsigned long long vm = P.active, need = 0;
+            if (v < P.n) {
+                vm = P.vis[v];
+                need = P.active & ~vm;
+            }
+            if (!__ballot(need != 0)) continue;
+            const int dg = need ? P.deg[v] : 0;
+            long long s = 0;
+            unsigned long long found = 0;
+            const bool hub = dg > P.hub_deg;
+            if (hub) {
+                found = next[v];        // from the chunk scans of this layer
+                need = 0;
+            }
+            if (need && dg > 0) s = P.off[v];
+            if (need && dg > 0 && dg <= 32) {
+                const long long e = s + dg;
+                unsigned long long rem = need;
+                for (long long j0 = s; j0 < e && rem; j0 += 4) {
+                    int uq[4];
+                    unsigned long long fq[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) uq[q] = j0 + q < e ? P.col[j0 + q] : -1;
+                    bool in[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) in[q] = uq[q] >= 0 && test_bit(ufront, uq[q]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) fq[q] = in[q] ? front[uq[q]] : 0ull;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const unsigned long long f = fq[q] & rem;
+                        if (f) {
+                            if (STAGED) {
+                                unsigned long long bits = f;
+                                while (bits) {
+                                    const int b = __ffsll((long long)bits) - 1;
+                                    bits &= bits - 1;
+                                    spos[b * 64 + lane] = (unsigned char)(j0 + q - s);
+                                }
+                            } else {
+                                emit_parent(P, v, uq[q], f);
+                            }
+                            found |= f;
+                            rem &= ~f;
+                        }
+                    }
+                }
+            }
+            unsigned long long longm = __ballot(need != 0 && dg > 32);   // up to hub_deg
+            while (longm) {
+                const int k = __ffsll((long long)longm) - 1;
+                longm &= longm - 1;
+                const long long vk = bcast64(v, k);
+                const long long sk = bcast64(s, k);
+                const long long ek = sk + __builtin_amdgcn_readlane(dg, k);
+                unsigned long long remk = bcast_u64(need, k);
+                unsigned long long foundk = 0;
+                for (long long b = sk; b < ek && remk; b += 64) {
+                    const long long j = b + lane;
+                    int u = 0;
+                    unsigned long long f = 0;
+                    if (j < ek) {
+                        u = P.col[j];
+                        if (test_bit(ufront, u)) f = front[u] & remk;
+                    }
+                    if (!__ballot(f != 0)) continue;
+                    unsigned long long newb = f & ~wave_excl_or(f);
+                    if (STAGED) {
+                        while (newb) {
+                            const int bb = __ffsll((long long)newb) - 1;
+                            newb &= newb - 1;
+                            spos[bb * 64 + k] = (unsigned char)(j - sk);
+                        }
+                    } else if (newb) {
+                        emit_parent(P, vk, u, newb);
+                    }
+                    const unsigned long long all = wave_or_u64(f);
+                    remk &= ~all;
+                    foundk |= all;
+                }
+                if (lane == k) found |= foundk;
+            }
+            const unsigned long long mine = hub ? 0ull : found;
+            if (STAGED) {
+                // LDS writes of other lanes above must be complete before the reads
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                unsigned long long all = wave_or_u64(mine);
+                while (all) {
+                    const int b = __ffsll((long long)all) - 1;
+                    all &= all - 1;
+                    if ((mine >> b) & 1ull) {
+                        const long long i = (long long)b * P.n + v;
+                        P.parent[i] = P.col[s + spos[b * 64 + lane]];
+                        P.level[i] = d + 1;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            } else {
+                store_levels(P, v, d, mine);
+            }
+            if (found) {
+                if (!hub) next[v] = found;
+                P.vis[v] = vm | found;
+                account(P, vm, found, dg, cnt);
+            }
+            const unsigned long long um = __ballot(found != 0);
+            if (lane == 0 && um) unext[w] = um;
+        }
+    }
+}
+
+// Pull for layer d: F_{d+1} into vis, its counters, and the buffers of F_{d-1}
+// cleared for reuse as `next` of layer d+1.
+template <bool STAGED>
 static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, long long gwave,
-                                  long long nwaves, long long gt, long long nt, bool leader,
-                                  BView *view, unsigned long long *s_red, int nwaves_block,
-                                  bool coherent)
+                                  long long nwaves, bool leader, BView *view, unsigned long long *s_red,
+                                  int nwaves_block, bool coherent, unsigned char *spos)
 {
     load_view(Pin, parity, d_hint, view, coherent);
     if (view->done) return;
@@ -230,83 +502,24 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
     unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
     unsigned long long *uspare = P.ubm + (long long)((d + 2) % 3) * P.W;
     unsigned long long cnt[6] = {0, 0, 0, 0, 0, 0};
-    const int G = P.wpg;
-    for (long long base = gwave * G; base < P.W; base += nwaves * G) {
-        for (int wi = 0; wi < G; ++wi) {
-            const long long w = base + wi;
-            if (w >= P.W) break;
-            const long long v = (w << 6) + lane;
-            const bool inr = v < P.n;
-            unsigned long long vm = P.active, need = 0;
-            if (inr) {
-                vm = P.vis[v];
-                need = cur == DIR_TD ? next[v] : (P.active & ~vm);
-            }
-            if (!__ballot(need != 0)) continue;
-            const int dg = need ? P.deg[v] : 0;
-            long long s = 0;
-            if (need && dg > 0) s = P.off[v];
-            unsigned long long found = 0;
-            // short rows: one lane scans its own row
-            if (need && dg > 0 && dg <= 32) {
-                unsigned long long rem = need;
-                for (long long j = s; j < s + dg; ++j) {
-                    const int u = P.col[j];
-                    const unsigned long long f = front[u] & rem;
-                    if (f) {
-                        emit(P, v, u, d, f);
-                        found |= f;
-                        rem &= ~f;
-                        if (!rem) break;
-                    }
-                }
-            }
-            // long rows: the whole wavefront, 64 entries per step
-            unsigned long long longm = __ballot(need != 0 && dg > 32);
-            while (longm) {
-                const int k = __ffsll((long long)longm) - 1;
-                longm &= longm - 1;
-                const long long vk = bcast64(v, k);
-                const long long sk = bcast64(s, k);
-                const long long ek = sk + __builtin_amdgcn_readlane(dg, k);
-                unsigned long long remk = bcast_u64(need, k);
-                unsigned long long foundk = 0;
-                for (long long b = sk; b < ek && remk; b += 64) {
-                    const long long j = b + lane;
-                    int u = 0;
-                    unsigned long long f = 0;
-                    if (j < ek) {
-                        u = P.col[j];
-                        f = front[u] & remk;
-                    }
-                    const unsigned long long newb = f & ~wave_excl_or(f);
-                    if (newb) emit(P, vk, u, d, newb);
-                    const unsigned long long all = wave_or_u64(f);
-                    remk &= ~all;
-                    foundk |= all;
-                }
-                if (lane == k) found |= foundk;
-            }
-            if (found) {
-                if (cur != DIR_TD) next[v] = found;     // push already stored it
-                P.vis[v] = vm | found;
-                const unsigned long long np = (unsigned long long)__popcll(found);
-                cnt[0] += np;
-                cnt[5] += np * (unsigned long long)dg;
-                cnt[1] += 1;
-                cnt[2] += (unsigned long long)dg;
-                cnt[3] += ((vm | found) == P.active) ? (unsigned long long)dg : 0ull;
-                cnt[4] += dg > P.hub_deg;
-            }
-            // every lane pushed here has a frontier neighbour in its row
-            if (cur == DIR_TD && found != need) atomicOr((unsigned *)&C->status, 32u);
-            const unsigned long long um = __ballot(found != 0);
-            if (lane == 0 && um) unext[w] = um;
+    if (cur == DIR_TD)
+        pull_after_push(P, next, unext, gwave, nwaves, cnt);
+    else
+        pull_bottom_up<STAGED>(P, d, front, P.ubm + (long long)(d % 3) * P.W, next, unext, gwave, nwaves, cnt,
+                               spos);
+    // F_{d-1}: its masks are nonzero exactly at the vertices its bitmap marks
+    for (long long base = gwave * 64; base < P.W; base += nwaves * 64) {
+        const long long myw = base + lane;
+        const unsigned long long sw = myw < P.W ? uspare[myw] : 0ull;
+        unsigned long long todo = __ballot(sw != 0);
+        while (todo) {
+            const int k = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const unsigned long long bits = bcast_u64(sw, k);
+            if ((bits >> lane) & 1ull) spare[((base + k) << 6) + lane] = 0ull;
         }
+        if (sw) uspare[myw] = 0ull;
     }
-    // clear the buffers that become `next` in layer d+1
-    for (long long i = gt; i < P.n; i += nt) spare[i] = 0ull;
-    for (long long i = gt; i < P.W; i += nt) uspare[i] = 0ull;
     if (leader) {
         BLayerState Nx = view->S;
         Nx.d = d + 1;
@@ -372,12 +585,15 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P)
         // vertices without edges count as visited in every lane: they are
         // never reached (a root among them is seeded separately)
         P.vis[v] = test_bit(P.iso, (int)v) ? P.active : 0ull;
+        // every layer clears only what it set, so all three buffers start empty
         P.fm[v] = 0ull;
         P.fm[P.n + v] = 0ull;
+        P.fm[2 * P.n + v] = 0ull;
     }
     for (long long w = gt; w < P.W; w += nt) {
         P.ubm[w] = 0ull;
         P.ubm[P.W + w] = 0ull;
+        P.ubm[2 * P.W + w] = 0ull;
     }
     if (gt == 0) {
         BCtrl *C = P.ctrl;
@@ -460,16 +676,16 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_push_kernel(BParams P, int l
     batch_push(P, layer & 1, layer, gwave, nwaves, blockIdx.x == 0 && threadIdx.x == 0, &view, false);
 }
 
-__global__ void __launch_bounds__(kBlock) bfs_batch_pull_kernel(BParams P, int layer)
+__global__ void __launch_bounds__(kPullWaves * 64) bfs_batch_pull_kernel(BParams P, int layer)
 {
     __shared__ BView view;
-    __shared__ unsigned long long s_red[6 * kWavesPerBlock];
-    const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
-    const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
-    const long long nt = (long long)gridDim.x * kBlock;
-    batch_pull(P, layer & 1, layer, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, &view,
-               s_red, kWavesPerBlock, false);
+    __shared__ unsigned long long s_red[6 * kPullWaves];
+    __shared__ unsigned char s_pos[kPullWaves][64 * 64];
+    const int wib = threadIdx.x >> 6;
+    const long long gwave = (long long)blockIdx.x * kPullWaves + wib;
+    const long long nwaves = (long long)gridDim.x * kPullWaves;
+    batch_pull<true>(P, layer & 1, layer, gwave, nwaves, blockIdx.x == 0 && threadIdx.x == 0, &view, s_red,
+                     kPullWaves, false, s_pos[wib]);
 }
 
 // One block runs whatever layers remain, with block barriers between phases.
@@ -487,8 +703,8 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_batch_finish_kernel(BParams 
         __syncthreads();
         if (!batch_push(P, parity, -1, gwave, nwaves, threadIdx.x == 0, &view, true)) break;
         __syncthreads();
-        batch_pull(P, parity, -1, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, &view, s_red,
-                   kFinishBlock / 64, true);
+        batch_pull<false>(P, parity, -1, gwave, nwaves, threadIdx.x == 0, &view, s_red, kFinishBlock / 64, true,
+                          nullptr);
         __syncthreads();
     }
 }
@@ -513,7 +729,7 @@ hipError_t launch_batch_push(const BParams &p, int layer, int grid, hipStream_t 
 
 hipError_t launch_batch_pull(const BParams &p, int layer, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(bfs_batch_pull_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer);
+    hipLaunchKernelGGL(bfs_batch_pull_kernel, dim3(grid), dim3(kPullWaves * 64), 0, s, p, layer);
     return hipGetLastError();
 }
 
@@ -525,11 +741,17 @@ hipError_t launch_batch_finish(const BParams &p, hipStream_t s)
 
 int batch_blocks_per_cu()
 {
-    int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, bfs_batch_pull_kernel, kBlock, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, bfs_batch_push_kernel, kBlock, 0) != hipSuccess)
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, bfs_batch_push_kernel, kBlock, 0) != hipSuccess) return -1;
+    return b;
+}
+
+int batch_pull_blocks_per_cu()
+{
+    int a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, bfs_batch_pull_kernel, kPullWaves * 64, 0) != hipSuccess)
         return -1;
-    return a < b ? a : b;
+    return a;
 }
 
 }  // namespace hybfs

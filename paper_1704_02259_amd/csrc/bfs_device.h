@@ -166,9 +166,11 @@ struct BParams {
 hipError_t launch_batch_init(const BParams &p, int grid, hipStream_t s);
 hipError_t launch_batch_seed(const BParams &p, const RootSet &roots, hipStream_t s);
 hipError_t launch_batch_push(const BParams &p, int layer, int grid, hipStream_t s);
-hipError_t launch_batch_pull(const BParams &p, int layer, int grid, hipStream_t s);
+hipError_t launch_batch_pull(const BParams &p, int layer, int grid, hipStream_t s);   // blocks of kPullWaves waves
 hipError_t launch_batch_finish(const BParams &p, hipStream_t s);
 int batch_blocks_per_cu();
+int batch_pull_blocks_per_cu();
+constexpr int kPullWaves = 4;             // wavefronts per block of the batched pull kernel
 
 // Launchers (defined in bfs_kernels.hip).
 hipError_t launch_init(const Params &p, int grid, hipStream_t s);

@@ -489,6 +489,9 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     const int bper_cu = batch_blocks_per_cu();
     if (bper_cu < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
     g->batch_grid = std::min(bper_cu, 4) * cus;
+    const int pper_cu = batch_pull_blocks_per_cu();
+    if (pper_cu < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
+    g->batch_pull_grid = pper_cu * cus;
     *out = reinterpret_cast<bfs_graph_t>(g.release());
     return BFS_OK;
 }

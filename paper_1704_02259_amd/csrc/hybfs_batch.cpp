@@ -101,6 +101,7 @@ static int enqueue_group(Graph *g, BatchWorkspace *w, const bfs_options &opt, co
     RootSet R;
     for (int i = 0; i < kLanes; ++i) R.r[i] = i < k ? roots[i] : -1;
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_grid;
+    const int pgrid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_pull_grid;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->batch_depth.typical.load();
     hipError_t e;
     if (profile) {
@@ -115,7 +116,7 @@ static int enqueue_group(Graph *g, BatchWorkspace *w, const bfs_options &opt, co
     for (int i = 0; i < L; ++i) {
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i], s)) != hipSuccess) return hip_fail(e, "event");
         if ((e = launch_batch_push(P, i, grid, s)) != hipSuccess) return hip_fail(e, "batch push launch");
-        if ((e = launch_batch_pull(P, i, grid, s)) != hipSuccess) return hip_fail(e, "batch pull launch");
+        if ((e = launch_batch_pull(P, i, pgrid, s)) != hipSuccess) return hip_fail(e, "batch pull launch");
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i + 1], s)) != hipSuccess) return hip_fail(e, "event");
     }
     if ((e = launch_batch_finish(P, s)) != hipSuccess) return hip_fail(e, "batch finisher launch");

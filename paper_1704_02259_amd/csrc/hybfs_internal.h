@@ -17,7 +17,9 @@ namespace hybfs {
 
 constexpr int kTraceCap = 4096;      // per-layer trace records kept on the device
 constexpr int kChunkLog2 = 8;        // top-down hub chunks cover 256 edges
-constexpr int kHubDegree = 256;      // top-down: above this degree, edges go through the hub table
+constexpr int kHubDegree = 256;      // above this degree, rows are split into hub-table chunks
+// the batched bottom-up keeps a row position below hub_deg in one byte
+static_assert(kHubDegree <= 256, "batched pull stages row positions as bytes");
 
 // Per-stream scratch of a single-root traversal.
 struct Workspace {
@@ -96,7 +98,8 @@ struct Graph {
     int wpg_default = 1;
     DepthTracker depth;                  // single-root traversals
     DepthTracker batch_depth;            // batched traversals
-    int batch_grid = 0;
+    int batch_grid = 0;                  // blocks of the batched push kernel
+    int batch_pull_grid = 0;             // blocks of the batched pull kernel (kPullWaves waves each)
     std::mutex mu;
     std::map<void *, std::unique_ptr<Workspace>> ws;
     std::map<void *, std::unique_ptr<BatchWorkspace>> bws;
