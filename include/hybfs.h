@@ -225,6 +225,97 @@ int bfs_run(bfs_graph_t g, int32_t root, int32_t *level_out, int32_t *parent_out
 int bfs_run_batch(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t *level_out,
                   int32_t *parent_out, const bfs_options *opt, bfs_stats *stats);
 
+/* ---- serving (continuous batching over resident graphs) ----
+ *
+ * A server holds graphs that are already resident (bfs_graph_create) and
+ * answers single-root BFS queries on them.  `streams` worker slots, each
+ * with its own HIP stream and host thread, run traversals concurrently, so
+ * the kernels of different queries overlap on the device.  A free slot takes
+ * the graph whose oldest queued query has waited longest and drains up to
+ * max_batch queued queries of that graph into one traversal: bfs_run for a
+ * single query, the batched multi-source traversal (bfs_run_batch) for more.
+ * Queries that arrive while others run wait for the next free slot
+ * (continuous batching).  Admission by memory: the traversals in flight hold
+ * at most memory_budget device bytes, counting each one's workspace and, for
+ * host outputs, its output staging; a batch that does not fit is halved, and
+ * a slot waits for running traversals to finish when not even one query
+ * fits.  Every answer equals bfs_run's for the same graph and root, byte for
+ * byte, whatever else is in flight.
+ */
+typedef struct bfs_server *bfs_server_t;
+
+typedef struct bfs_serve_config {
+    int64_t memory_budget;   /* device bytes for traversals in flight; 0 = 75% of the
+                                free device memory when the server is created */
+    int32_t max_batch;       /* queries per traversal, 1..64 (default 64) */
+    int32_t streams;         /* worker slots, 1..16 (default 4) */
+    int32_t queue_capacity;  /* queued + running queries before submit returns
+                                BFS_E_BUSY, >= 1 (default 65536) */
+    int32_t out_on_device;   /* 1 (default): level_out / parent_out of every query are
+                                device pointers; 0: host pointers */
+    int32_t alpha;           /* switch parameters of Algorithm 3's edge rule, 0 = the */
+    int32_t beta;            /* bfs_options defaults */
+} bfs_serve_config;
+
+/* Defaults: budget 0 (75% of free memory), max_batch 64, 4 streams, queue
+ * capacity 65536, device outputs, default alpha and beta. */
+void bfs_serve_config_init(bfs_serve_config *cfg);
+
+typedef struct bfs_serve_report {
+    int64_t submitted;       /* since creation or the last bfs_serve_reset_stats */
+    int64_t completed;       /* finished with BFS_OK */
+    int64_t failed;          /* finished with an error */
+    int64_t queued;          /* waiting now */
+    int64_t running;         /* in flight now */
+    int64_t batches;         /* traversals launched (single or batched) */
+    int64_t batched_requests;/* queries answered by a traversal of more than one root */
+    int64_t admission_waits; /* times a slot waited for memory to free up */
+    int64_t bytes_in_use;    /* device bytes charged by traversals in flight now */
+    int64_t peak_bytes;      /* maximum of bytes_in_use */
+    int64_t memory_budget;
+    double  p50_us;          /* latency = completion - submission (host monotonic clock), */
+    double  p99_us;          /* over completed queries */
+    double  mean_us;
+    double  max_us;
+    double  traversed_edges; /* sum over completed queries of half the reached degree sum */
+    double  gteps;           /* traversed_edges / (last completion - first submission) / 1e9 */
+} bfs_serve_report;
+
+/* Create a server on the current HIP device.  cfg may be NULL (defaults).
+ * Errors: BFS_E_INVALID (a field out of range), BFS_E_NOMEM, BFS_E_DEVICE. */
+int bfs_serve_create(const bfs_serve_config *cfg, bfs_server_t *out);
+
+/* Register a resident graph; *graph_id receives its id (0, 1, ...).  The
+ * caller keeps ownership and must not destroy the graph before the server. */
+int bfs_serve_add_graph(bfs_server_t s, bfs_graph_t g, int32_t *graph_id);
+
+/* Queue one BFS query.  level_out / parent_out: int32[n] each, caller-owned,
+ * device or host pointers as configured; they must stay valid until the
+ * query completes.  *ticket identifies the query.  Errors: BFS_E_NOTFOUND
+ * (graph id), BFS_E_INVALID (root out of range, NULL pointer), BFS_E_BUSY
+ * (queue_capacity reached). */
+int bfs_serve_submit(bfs_server_t s, int32_t graph_id, int32_t root, int32_t *level_out,
+                     int32_t *parent_out, uint64_t *ticket);
+
+/* *done = 1 once the query has finished; the call that reports completion
+ * releases the ticket and returns the query's own status (BFS_OK or its
+ * error).  Unknown or released ticket: BFS_E_NOTFOUND. */
+int bfs_serve_poll(bfs_server_t s, uint64_t ticket, int32_t *done);
+
+/* Block until the query finishes (timeout_us < 0: no limit), release the
+ * ticket and return the query's status; BFS_E_TIMEOUT leaves it pending. */
+int bfs_serve_wait(bfs_server_t s, uint64_t ticket, int64_t timeout_us);
+
+/* Counters and latency percentiles (see bfs_serve_report). */
+int bfs_serve_stats(bfs_server_t s, bfs_serve_report *out);
+
+/* Zero the counters and latencies (e.g. after warm-up queries). */
+int bfs_serve_reset_stats(bfs_server_t s);
+
+/* Finish every queued and running query, then stop the workers and free the
+ * server (graphs are not freed). */
+int bfs_serve_destroy(bfs_server_t s);
+
 /* Wait for all work enqueued on `stream` for this graph and report any
  * failure of asynchronous runs (BFS_E_DEVICE). */
 int bfs_graph_sync(bfs_graph_t g, void *stream);

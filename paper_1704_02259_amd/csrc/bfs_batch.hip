@@ -61,7 +61,7 @@ static __device__ __forceinline__ void emit_parent(const BParams &P, long long v
     while (bits) {
         const int b = __ffsll((long long)bits) - 1;
         bits &= bits - 1;
-        P.parent[(long long)b * P.n + v] = u;
+        P.par[b][v] = u;
     }
 }
 
@@ -74,7 +74,7 @@ static __device__ __forceinline__ void store_levels(const BParams &P, long long 
     while (all) {
         const int b = __ffsll((long long)all) - 1;
         all &= all - 1;
-        if ((found >> b) & 1ull) P.level[(long long)b * P.n + v] = d + 1;
+        if ((found >> b) & 1ull) P.lvl[b][v] = d + 1;
     }
 }
 
@@ -93,9 +93,8 @@ static __device__ __forceinline__ void td_discover(const BParams &P, unsigned lo
     while (m) {
         const int b = __ffsll((long long)m) - 1;
         m &= m - 1;
-        const long long i = (long long)b * P.n + v;
-        atomicMin((unsigned *)&P.parent[i], (unsigned)u);
-        if ((fresh >> b) & 1ull) P.level[i] = d + 1;
+        atomicMin((unsigned *)&P.par[b][v], (unsigned)u);
+        if ((fresh >> b) & 1ull) P.lvl[b][v] = d + 1;
     }
 }
 
@@ -135,9 +134,8 @@ static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gw
             while (newb) {
                 const int bb = __ffsll((long long)newb) - 1;
                 newb &= newb - 1;
-                const long long i = (long long)bb * P.n + v;
-                atomicMin((unsigned *)&P.parent[i], (unsigned)u);
-                P.level[i] = d + 1;
+                atomicMin((unsigned *)&P.par[bb][v], (unsigned)u);
+                P.lvl[bb][v] = d + 1;
             }
             const unsigned long long all = wave_or_u64(f);
             rem &= ~all;
@@ -153,8 +151,6 @@ static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gw
 struct BView {
     int done;
     int pad;
-    int *level;
-    int *parent;
     BLayerState S;
     long long c[6];
 };
@@ -167,8 +163,6 @@ static __device__ void load_view(const BParams &P, int parity, int d_hint, BView
     if (threadIdx.x == 0) {
         BCtrl *C = P.ctrl;
         view->done = C->done;
-        view->level = C->level;
-        view->parent = C->parent;
         view->S = C->st[parity];
         BSlot &sl = C->slot[view->S.d % kSlots];
         for (int j = 0; j < 6; ++j) {
@@ -187,9 +181,7 @@ static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, lo
 {
     load_view(Pin, parity, d_hint, view, coherent);
     if (view->done) return false;
-    BParams P = Pin;
-    P.level = view->level;
-    P.parent = view->parent;
+    const BParams &P = Pin;
     BCtrl *C = P.ctrl;
     const int d = view->S.d;
     if (d_hint >= 0 && d != d_hint) {
@@ -456,9 +448,8 @@ static __device__ void pull_bottom_up(const BParams &P, int d, const unsigned lo
                     const int b = __ffsll((long long)all) - 1;
                     all &= all - 1;
                     if ((mine >> b) & 1ull) {
-                        const long long i = (long long)b * P.n + v;
-                        P.parent[i] = P.col[s + spos[b * 64 + lane]];
-                        P.level[i] = d + 1;
+                        P.par[b][v] = P.col[s + spos[b * 64 + lane]];
+                        P.lvl[b][v] = d + 1;
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -486,9 +477,7 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
 {
     load_view(Pin, parity, d_hint, view, coherent);
     if (view->done) return;
-    BParams P = Pin;
-    P.level = view->level;
-    P.parent = view->parent;
+    const BParams &P = Pin;
     BCtrl *C = P.ctrl;
     const int d = view->S.d;
     if (d_hint >= 0 && d != d_hint) return;
@@ -565,21 +554,28 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P)
+// Grid (x, k + 1): row y < k fills lane y's outputs with -1; row k clears
+// the masks and bitmaps, stores the output table and resets the control block.
+__global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P, LanePtrs out)
 {
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
-    const long long total = (long long)P.k * P.n;
-    const bool vec = ((((unsigned long long)P.level) | ((unsigned long long)P.parent)) & 15ull) == 0;
-    const long long n4 = vec ? (total >> 2) : 0;
-    const int4 m1 = make_int4(-1, -1, -1, -1);
-    for (long long i = gt; i < n4; i += nt) {
-        ((int4 *)P.level)[i] = m1;
-        ((int4 *)P.parent)[i] = m1;
-    }
-    for (long long i = (n4 << 2) + gt; i < total; i += nt) {
-        P.level[i] = -1;
-        P.parent[i] = -1;
+    const int y = blockIdx.y;
+    if (y < P.k) {
+        int *lv = out.level[y];
+        int *pa = out.parent[y];
+        const bool vec = ((((unsigned long long)lv) | ((unsigned long long)pa)) & 15ull) == 0;
+        const long long n4 = vec ? (P.n >> 2) : 0;
+        const int4 m1 = make_int4(-1, -1, -1, -1);
+        for (long long i = gt; i < n4; i += nt) {
+            ((int4 *)lv)[i] = m1;
+            ((int4 *)pa)[i] = m1;
+        }
+        for (long long i = (n4 << 2) + gt; i < P.n; i += nt) {
+            lv[i] = -1;
+            pa[i] = -1;
+        }
+        return;
     }
     for (long long v = gt; v < P.n; v += nt) {
         // vertices without edges count as visited in every lane: they are
@@ -595,14 +591,16 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P)
         P.ubm[P.W + w] = 0ull;
         P.ubm[2 * P.W + w] = 0ull;
     }
+    if (gt < kLanes) {
+        const_cast<int **>(P.lvl)[gt] = gt < P.k ? out.level[gt] : nullptr;
+        const_cast<int **>(P.par)[gt] = gt < P.k ? out.parent[gt] : nullptr;
+    }
     if (gt == 0) {
         BCtrl *C = P.ctrl;
         C->done = 0;
         C->nlayers = 0;
         C->parity = 0;
         C->status = 0;
-        C->level = P.level;
-        C->parent = P.parent;
         C->pairs = 0;
         C->pairs_deg = 0;
         BLayerState S;
@@ -637,8 +635,8 @@ __global__ void __launch_bounds__(64) bfs_batch_seed_kernel(BParams P, RootSet R
     }
     unsigned long long c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
     if (on) {
-        P.level[(long long)lane * P.n + r] = 0;
-        P.parent[(long long)lane * P.n + r] = r;
+        P.lvl[lane][r] = 0;
+        P.par[lane][r] = r;
         c5 = (unsigned long long)P.deg[r];
     }
     if (first) {
@@ -709,9 +707,9 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_batch_finish_kernel(BParams 
     }
 }
 
-hipError_t launch_batch_init(const BParams &p, int grid, hipStream_t s)
+hipError_t launch_batch_init(const BParams &p, const LanePtrs &out, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(bfs_batch_init_kernel, dim3(grid), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(bfs_batch_init_kernel, dim3(grid, p.k + 1), dim3(kBlock), 0, s, p, out);
     return hipGetLastError();
 }
 

@@ -124,8 +124,7 @@ struct BCtrl {
     int nlayers;
     int parity;
     int status;
-    int *level;
-    int *parent;
+    long long pad0[2];
     long long pairs;
     long long pairs_deg;
     long long pad[4];
@@ -135,6 +134,12 @@ struct BCtrl {
 
 struct RootSet {
     int r[kLanes];
+};
+
+// Output arrays of each lane: level_b[n] and parent_b[n] of root b.
+struct LanePtrs {
+    int *level[kLanes];
+    int *parent[kLanes];
 };
 
 struct BParams {
@@ -153,7 +158,8 @@ struct BParams {
     unsigned long long *vis;             // [n] lanes that reached v in a finished layer
     unsigned long long *fm;              // [3n] rotating lane masks: frontier / next / spare
     unsigned long long *ubm;             // [3W] rotating bitmaps: vertex has a nonzero mask
-    int *level, *parent;                 // outputs [k * n], root-major
+    int *const *lvl;                     // device table [kLanes]: lane b's level array
+    int *const *par;                     // device table [kLanes]: lane b's parent array
     BCtrl *ctrl;
     LayerRec *trace;
     int trace_cap;
@@ -163,7 +169,8 @@ struct BParams {
     long long alpha, beta;
 };
 
-hipError_t launch_batch_init(const BParams &p, int grid, hipStream_t s);
+// The init kernel copies `out` into the device tables p.lvl / p.par.
+hipError_t launch_batch_init(const BParams &p, const LanePtrs &out, int grid, hipStream_t s);
 hipError_t launch_batch_seed(const BParams &p, const RootSet &roots, hipStream_t s);
 hipError_t launch_batch_push(const BParams &p, int layer, int grid, hipStream_t s);
 hipError_t launch_batch_pull(const BParams &p, int layer, int grid, hipStream_t s);   // blocks of kPullWaves waves

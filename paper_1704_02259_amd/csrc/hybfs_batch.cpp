@@ -22,10 +22,11 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t batch_workspace_bytes(long long n, long long W)
 {
     return align256((size_t)n * 8) + align256((size_t)n * 8 * 3) + align256((size_t)W * 8 * 3) +
-           align256(sizeof(BCtrl)) + align256((size_t)kTraceCap * sizeof(LayerRec));
+           align256(sizeof(BCtrl)) + align256((size_t)kTraceCap * sizeof(LayerRec)) +
+           align256(2 * kLanes * sizeof(int *));
 }
 
-static int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
+int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
 {
     std::lock_guard<std::mutex> lk(g->mu);
     auto it = g->bws.find(stream);
@@ -52,7 +53,8 @@ static int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
     w->fm = (unsigned long long *)(b + o);   o += align256((size_t)n * 8 * 3);
     w->ubm = (unsigned long long *)(b + o);  o += align256((size_t)W * 8 * 3);
     w->ctrl = (BCtrl *)(b + o);              o += align256(sizeof(BCtrl));
-    w->trace = (LayerRec *)(b + o);
+    w->trace = (LayerRec *)(b + o);          o += align256((size_t)kTraceCap * sizeof(LayerRec));
+    w->tab = (int **)(b + o);
     if ((e = hipMemset(w->ctrl, 0, sizeof(BCtrl))) != hipSuccess) return hip_fail(e, "workspace init");
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "workspace init");
     *out = w.get();
@@ -61,7 +63,7 @@ static int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
 }
 
 static void fill_batch_params(const Graph *g, const BatchWorkspace *w, const bfs_options &opt, int k,
-                              int *lvl, int *par, BParams *P)
+                              BParams *P)
 {
     std::memset(P, 0, sizeof *P);
     P->n = g->n;
@@ -81,8 +83,8 @@ static void fill_batch_params(const Graph *g, const BatchWorkspace *w, const bfs
     P->vis = w->vis;
     P->fm = w->fm;
     P->ubm = w->ubm;
-    P->level = lvl;
-    P->parent = par;
+    P->lvl = w->tab;
+    P->par = w->tab + kLanes;
     P->ctrl = w->ctrl;
     P->trace = w->trace;
     P->trace_cap = kTraceCap;
@@ -93,11 +95,11 @@ static void fill_batch_params(const Graph *g, const BatchWorkspace *w, const bfs
 }
 
 // [init, seed, L x (push, pull), finisher] for one group of at most 64 roots.
-static int enqueue_group(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
-                         int *lvl, int *par, hipStream_t s, bool profile, int *layers_enqueued)
+int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
+                  const LanePtrs &out, hipStream_t s, bool profile, int *layers_enqueued)
 {
     BParams P;
-    fill_batch_params(g, w, opt, k, lvl, par, &P);
+    fill_batch_params(g, w, opt, k, &P);
     RootSet R;
     for (int i = 0; i < kLanes; ++i) R.r[i] = i < k ? roots[i] : -1;
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_grid;
@@ -111,7 +113,7 @@ static int enqueue_group(Graph *g, BatchWorkspace *w, const bfs_options &opt, co
             w->layer_ev.push_back(ev);
         }
     }
-    if ((e = launch_batch_init(P, grid, s)) != hipSuccess) return hip_fail(e, "batch init launch");
+    if ((e = launch_batch_init(P, out, grid, s)) != hipSuccess) return hip_fail(e, "batch init launch");
     if ((e = launch_batch_seed(P, R, s)) != hipSuccess) return hip_fail(e, "batch seed launch");
     for (int i = 0; i < L; ++i) {
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i], s)) != hipSuccess) return hip_fail(e, "event");
@@ -193,7 +195,12 @@ int bfs_run_batch(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t *leve
         int *par = opt.out_on_device ? parent_out + (long long)g0 * n : stage + (long long)kg * n;
         int launched = 0;
         if ((e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
-        rc = enqueue_group(g, w, opt, roots + g0, kg, lvl, par, s, profile, &launched);
+        LanePtrs out;
+        for (int b = 0; b < kLanes; ++b) {
+            out.level[b] = b < kg ? lvl + (long long)b * n : nullptr;
+            out.parent[b] = b < kg ? par + (long long)b * n : nullptr;
+        }
+        rc = enqueue_batch(g, w, opt, roots + g0, kg, out, s, profile, &launched);
         if (rc) return rc;
         if ((e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
         if (opt.async) continue;

@@ -57,6 +57,7 @@ struct BatchWorkspace {
     unsigned long long *ubm = nullptr;   // [3W]
     BCtrl *ctrl = nullptr;
     LayerRec *trace = nullptr;
+    int **tab = nullptr;                 // device [2 * kLanes]: per-lane level, then parent arrays
     int *out_tmp = nullptr;              // host-output staging: level + parent of one group
     long long out_tmp_elems = 0;
     BCtrl *h_ctrl = nullptr;             // pinned
@@ -114,6 +115,9 @@ int check_csr(int64_t n, int64_t nnz, const int64_t *off, const int32_t *col, bo
               bool check_symmetry);
 int get_workspace(Graph *g, void *stream, Workspace **out);
 size_t batch_workspace_bytes(long long n, long long W);
+int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out);
+int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
+                  const LanePtrs &out, hipStream_t s, bool profile, int *layers_enqueued);
 void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P);
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
                       hipStream_t s, int *layers_enqueued, bool profile);

@@ -65,6 +65,20 @@ class bfs_graph_info(ctypes.Structure):
                 ("batch_workspace_bytes", ctypes.c_int64)]
 
 
+class bfs_serve_config(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("out_on_device", ctypes.c_int32), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32)]
+
+
+class bfs_serve_report(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "queued", "running",
+                                              "batches", "batched_requests", "admission_waits",
+                                              "bytes_in_use", "peak_bytes", "memory_budget")] + \
+               [(k, ctypes.c_double) for k in ("p50_us", "p99_us", "mean_us", "max_us", "traversed_edges",
+                                               "gteps")]
+
+
 class HybfsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"hybfs error {code}: {msg}")
@@ -95,6 +109,15 @@ def load():
         "bfs_run_batch": (ctypes.c_int, [vp, vp, i32, vp, vp, ctypes.POINTER(bfs_options),
                                          ctypes.POINTER(bfs_stats)]),
         "bfs_graph_sync": (ctypes.c_int, [vp, vp]),
+        "bfs_serve_config_init": (None, [ctypes.POINTER(bfs_serve_config)]),
+        "bfs_serve_create": (ctypes.c_int, [ctypes.POINTER(bfs_serve_config), ctypes.POINTER(vp)]),
+        "bfs_serve_add_graph": (ctypes.c_int, [vp, vp, ctypes.POINTER(i32)]),
+        "bfs_serve_submit": (ctypes.c_int, [vp, i32, i32, vp, vp, ctypes.POINTER(u64)]),
+        "bfs_serve_poll": (ctypes.c_int, [vp, u64, ctypes.POINTER(i32)]),
+        "bfs_serve_wait": (ctypes.c_int, [vp, u64, i64]),
+        "bfs_serve_stats": (ctypes.c_int, [vp, ctypes.POINTER(bfs_serve_report)]),
+        "bfs_serve_reset_stats": (ctypes.c_int, [vp]),
+        "bfs_serve_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -265,3 +288,57 @@ class Graph:
                                    "layer_kernel_us": st.layer_kernel_us,
                                    "layers": stats_layers(st, arr)}
         return level, parent
+
+
+class Server:
+    """BFS serving over resident graphs (wraps bfs_serve_*).  Output buffers
+    passed to submit() must stay alive until the query completes."""
+
+    def __init__(self, **cfg):
+        c = bfs_serve_config()
+        load().bfs_serve_config_init(ctypes.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        self.cfg = c
+        h = ctypes.c_void_p()
+        _check(load().bfs_serve_create(ctypes.byref(c), ctypes.byref(h)))
+        self.handle = h.value
+        self._graphs = []
+
+    def add_graph(self, G: Graph) -> int:
+        gid = ctypes.c_int32()
+        _check(load().bfs_serve_add_graph(self.handle, G.handle, ctypes.byref(gid)))
+        self._graphs.append(G)
+        return gid.value
+
+    def submit(self, graph_id: int, root: int, level_ptr: int, parent_ptr: int) -> int:
+        t = ctypes.c_uint64()
+        _check(load().bfs_serve_submit(self.handle, graph_id, root, level_ptr, parent_ptr, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(load().bfs_serve_poll(self.handle, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        _check(load().bfs_serve_wait(self.handle, ticket, timeout_us))
+
+    def stats(self) -> dict:
+        r = bfs_serve_report()
+        _check(load().bfs_serve_stats(self.handle, ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in r._fields_}
+
+    def reset_stats(self):
+        _check(load().bfs_serve_reset_stats(self.handle))
+
+    def close(self):
+        if self.handle:
+            _check(load().bfs_serve_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -90,6 +90,30 @@ def test_run_batch_rejects_null_graph(lib):
     assert rc == -1 and "graph" in lib.bfs_last_error().decode()
 
 
+def test_serve_create_rejects_bad_config(lib):
+    from paper_1704_02259_amd import hybfs
+    for field, value in (("max_batch", 0), ("max_batch", 65), ("streams", 0), ("streams", 17),
+                         ("queue_capacity", 0), ("out_on_device", 2), ("memory_budget", -1)):
+        cfg = hybfs.bfs_serve_config()
+        lib.bfs_serve_config_init(ctypes.byref(cfg))
+        setattr(cfg, field, value)
+        h = ctypes.c_void_p()
+        assert lib.bfs_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == -1, field
+    cfg = hybfs.bfs_serve_config()
+    lib.bfs_serve_config_init(ctypes.byref(cfg))
+    assert (cfg.max_batch, cfg.streams, cfg.queue_capacity, cfg.out_on_device) == (64, 4, 65536, 1)
+
+
+def test_serve_calls_reject_null_server(lib):
+    z = np.zeros(4, np.int32)
+    t = ctypes.c_uint64()
+    d = ctypes.c_int32()
+    assert lib.bfs_serve_submit(None, 0, 0, z.ctypes.data, z.ctypes.data, ctypes.byref(t)) == -1
+    assert lib.bfs_serve_poll(None, 1, ctypes.byref(d)) == -1
+    assert lib.bfs_serve_wait(None, 1, 0) == -1
+    assert lib.bfs_serve_destroy(None) == -1
+
+
 def test_binding_raises_without_library(tmp_path, monkeypatch):
     from paper_1704_02259_amd import hybfs
     monkeypatch.setattr(hybfs, "_lib", None)
