@@ -153,6 +153,8 @@ struct BView {
     int pad;
     BLayerState S;
     long long c[6];
+    int *lvl[kLanes];                    // the lanes' output arrays, from the device table
+    int *par[kLanes];
 };
 
 // Thread 0 reads the control data once per block; `coherent` reads the
@@ -160,6 +162,8 @@ struct BView {
 // whose own atomics may be newer than its L1).
 static __device__ void load_view(const BParams &P, int parity, int d_hint, BView *view, bool coherent)
 {
+    if (threadIdx.x < kLanes) view->lvl[threadIdx.x] = P.lvl[threadIdx.x];
+    else if (threadIdx.x < 2 * kLanes) view->par[threadIdx.x - kLanes] = P.par[threadIdx.x - kLanes];
     if (threadIdx.x == 0) {
         BCtrl *C = P.ctrl;
         view->done = C->done;
@@ -181,7 +185,9 @@ static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, lo
 {
     load_view(Pin, parity, d_hint, view, coherent);
     if (view->done) return false;
-    const BParams &P = Pin;
+    BParams P = Pin;
+    P.lvl = view->lvl;
+    P.par = view->par;
     BCtrl *C = P.ctrl;
     const int d = view->S.d;
     if (d_hint >= 0 && d != d_hint) {
@@ -477,7 +483,9 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
 {
     load_view(Pin, parity, d_hint, view, coherent);
     if (view->done) return;
-    const BParams &P = Pin;
+    BParams P = Pin;
+    P.lvl = view->lvl;
+    P.par = view->par;
     BCtrl *C = P.ctrl;
     const int d = view->S.d;
     if (d_hint >= 0 && d != d_hint) return;
