@@ -58,6 +58,160 @@ def measured_traffic(workload: str):
     return t.get("bytes_per_launch")
 
 
+def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
+    """Batched multi-source traversal against single-root runs on the same
+    roots: speedup = sum of single-root times / batch time, outputs equal."""
+    import inputs
+    g = inputs.workload_graph(workload)
+    roots = inputs.workload_roots(workload, g, k).astype(np.int32)
+    G = hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID)
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    lv = torch.empty((k, g.n), dtype=torch.int32, device=dev)
+    pa = torch.empty((k, g.n), dtype=torch.int32, device=dev)
+    blv = torch.empty((k, g.n), dtype=torch.int32, device=dev)
+    bpa = torch.empty((k, g.n), dtype=torch.int32, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    # single-root runs (warm-up pass adapts the launch depth), then timed
+    te = []
+    for i, r in enumerate(roots):
+        _, _, st = G.run(int(r), lv[i], pa[i], stream=sp, stats=True)
+        te.append(st["reached_degree_sum"] / 2.0)
+    t_single = np.zeros((reps, k))
+    for rep in range(reps):
+        for i, r in enumerate(roots):
+            a, b = ev(), ev()
+            a.record(stream)
+            G.run(int(r), lv[i], pa[i], stream=sp, async_=1)
+            b.record(stream)
+            stream.synchronize()
+            t_single[rep, i] = a.elapsed_time(b)
+    G.run_batch(roots, blv, bpa, stream=sp)      # warm-up, adapts the batch depth
+    t_batch = []
+    for rep in range(reps):
+        a, b = ev(), ev()
+        a.record(stream)
+        G.run_batch(roots, blv, bpa, stream=sp, async_=1)
+        b.record(stream)
+        stream.synchronize()
+        t_batch.append(a.elapsed_time(b))
+    equal = bool(torch.equal(lv, blv) and torch.equal(pa, bpa))
+    ts = float(np.median(t_single, axis=0).sum())
+    tb = float(np.median(t_batch))
+    G.close()
+    del lv, pa, blv, bpa
+    torch.cuda.empty_cache()
+    return {"workload": f"kronecker_scale{workload[4:]}_ef16_{k}roots", "roots": k,
+            "sum_single_ms": round(ts, 3), "batch_ms": round(tb, 3), "speedup": round(ts / tb, 3),
+            "gteps_batch": round(sum(te) / (tb * 1e-3) / 1e9, 2),
+            "gteps_single_aggregate": round(sum(te) / (ts * 1e-3) / 1e9, 2), "outputs_equal": equal}
+
+
+SERVE_GRAPHS = ["kron14", "kron16", "kron18", "kron20", "kron22", "er20"]
+
+
+def serving_leg(torch, hybfs, dev, queries=1000, warm=200, pool=96, streams=4, resident=None):
+    """Poisson stream of single-root queries over six resident graphs (graph
+    chosen with probability proportional to n, root uniform among degree > 0
+    vertices), served with continuous batching.  Saturation throughput comes
+    from a burst of all queries at once; then paced streams at 0.5x and 0.9x
+    of it report p50/p99 latency and GTEPS."""
+    import inputs
+    resident = resident or {}
+    gs, Gs = [], []
+    for name in SERVE_GRAPHS:
+        g = resident.get(name) or inputs.workload_graph(name)
+        gs.append(g)
+        Gs.append(hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID))
+    S = hybfs.Server(streams=streams, max_batch=64)
+    ids = [S.add_graph(G) for G in Gs]
+    w = np.array([g.n for g in gs], dtype=np.float64)
+    w /= w.sum()
+    rng = np.random.default_rng(inputs.SERVE_SEED)
+    live = [np.nonzero(np.diff(g.off) > 0)[0] for g in gs]
+
+    def draw(m):
+        out = []
+        for _ in range(m):
+            gi = int(rng.choice(len(gs), p=w))
+            out.append((gi, int(live[gi][rng.integers(len(live[gi]))])))
+        return out
+
+    bufs = [[(torch.empty(g.n, dtype=torch.int32, device=dev), torch.empty(g.n, dtype=torch.int32, device=dev))
+             for _ in range(pool)] for g in gs]
+    slot_ticket = [[None] * pool for _ in gs]
+    counters = [0] * len(gs)
+
+    def submit(gi, r):
+        j = counters[gi] % pool
+        counters[gi] += 1
+        if slot_ticket[gi][j] is not None:
+            S.wait(slot_ticket[gi][j])
+        lv, pa = bufs[gi][j]
+        t = S.submit(ids[gi], r, lv.data_ptr(), pa.data_ptr())
+        slot_ticket[gi][j] = t
+        return t, j
+
+    def drain():
+        for gi in range(len(gs)):
+            for j in range(pool):
+                if slot_ticket[gi][j] is not None:
+                    S.wait(slot_ticket[gi][j])
+                    slot_ticket[gi][j] = None
+
+    for gi, r in draw(warm):                       # warm-up: adapts launch depths
+        submit(gi, r)
+    drain()
+    burst = draw(queries)
+    S.reset_stats()
+    t0 = time.perf_counter()
+    for gi, r in burst:
+        submit(gi, r)
+    drain()
+    sat_qps = queries / (time.perf_counter() - t0)
+    sat = S.stats()
+    out = {"graphs": SERVE_GRAPHS, "streams": streams, "max_batch": 64, "queries": queries,
+           "saturation_qps": round(sat_qps, 1), "saturation_gteps": round(sat["gteps"], 2),
+           "saturation_p50_us": round(sat["p50_us"], 1), "saturation_p99_us": round(sat["p99_us"], 1),
+           "runs": []}
+    for frac in (0.5, 0.9):
+        lam = frac * sat_qps
+        qs = draw(queries)
+        gaps = rng.exponential(1.0 / lam, queries)
+        S.reset_stats()
+        t_next = time.perf_counter()
+        for (gi, r), gap in zip(qs, gaps):
+            t_next += gap
+            while time.perf_counter() < t_next:
+                pass
+            submit(gi, r)
+        drain()
+        st = S.stats()
+        out["runs"].append({"load": frac, "qps": round(lam, 1), "p50_us": round(st["p50_us"], 1),
+                            "p99_us": round(st["p99_us"], 1), "gteps": round(st["gteps"], 2),
+                            "mean_batch": round(st["completed"] / max(st["batches"], 1), 2),
+                            "completed": st["completed"], "failed": st["failed"]})
+    # served answers equal the same queries run alone
+    ok = True
+    check = draw(8)
+    tickets = [submit(gi, r) for gi, r in check]
+    drain()
+    for (gi, r), (_, j) in zip(check, tickets):
+        lv, pa = bufs[gi][j]
+        l1 = torch.empty_like(lv)
+        p1 = torch.empty_like(pa)
+        Gs[gi].run(r, l1, p1)
+        torch.cuda.synchronize()
+        ok &= bool(torch.equal(lv, l1) and torch.equal(pa, p1))
+    out["served_equal_alone"] = ok
+    S.close()
+    for G in Gs:
+        G.close()
+    del bufs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,12 +219,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="kron20", help="kron<S> (edgefactor 16) or er20")
     ap.add_argument("--roots", type=int, default=64)
-    ap.add_argument("--cpu-sample", type=int, default=16, help="roots timed on the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="roots timed on the CPU oracle")
     ap.add_argument("--balg-roots", type=int, default=64, help="roots whose algorithmic bytes are counted")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--alpha", type=int, default=0)
     ap.add_argument("--beta", type=int, default=0)
     ap.add_argument("--probe-k", type=int, default=-1)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-root leg (SCALE 22)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -197,14 +353,17 @@ def main():
         # exact TE and algorithmic bytes per root from the oracle (not timed)
         nb = min(args.balg_roots, len(roots))
 
-        def work(r):
+        def work(ir):
+            i, r = ir
             elv, _ = oracle.bfs(g, int(r))
             te_r = oracle.traversed_edges(g, elv)
-            res = oracle.algorithmic_bytes(g, elv) if nb else None
+            res = oracle.algorithmic_bytes(g, elv) if i < nb else None
+            if g.n >= (1 << 24):
+                log(f"oracle root {i}: TE {te_r:.0f}")
             return te_r, res
 
         with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-            outs = list(ex.map(work, [int(r) for r in roots]))
+            outs = list(ex.map(work, list(enumerate(int(r) for r in roots))))
         te = np.array([o[0] for o in outs])
         balg_layers = [sum(min(td, bu) for td, bu in o[1]["per_layer"]) for o in outs[:nb]]
         balg_total = [o[1]["bytes"] for o in outs[:nb]]
@@ -254,6 +413,14 @@ def main():
         "min_root_gteps": round(float(gteps.min()), 3),
         "parity_sample_ok": parity_ok,
     }
+    if not args.no_batch and args.workload == "kron20":
+        log("batched leg (SCALE 22, 64 roots) ...")
+        out["batched"] = batched_leg(torch, hybfs, dev)
+        log("batched:", out["batched"])
+    if not args.no_serve and args.workload == "kron20":
+        log("serving leg (6 graphs) ...")
+        out["serving"] = serving_leg(torch, hybfs, dev, resident={"kron20": g})
+        log("serving:", out["serving"])
     print(json.dumps(out), flush=True)
 
 

@@ -233,7 +233,8 @@ int bfs_run_batch(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t *level
  * the kernels of different queries overlap on the device.  A free slot takes
  * the graph whose oldest queued query has waited longest and drains up to
  * max_batch queued queries of that graph into one traversal: bfs_run for a
- * single query, the batched multi-source traversal (bfs_run_batch) for more.
+ * single query, the batched multi-source traversal (bfs_run_batch) for more
+ * (only once enough are queued, see batch_threshold).
  * Queries that arrive while others run wait for the next free slot
  * (continuous batching).  Admission by memory: the traversals in flight hold
  * at most memory_budget device bytes, counting each one's workspace and, for
@@ -255,6 +256,13 @@ typedef struct bfs_serve_config {
                                 device pointers; 0: host pointers */
     int32_t alpha;           /* switch parameters of Algorithm 3's edge rule, 0 = the */
     int32_t beta;            /* bfs_options defaults */
+    int32_t batch_threshold; /* queued queries of one graph from which a slot runs them
+                                as one batched traversal; below it a slot takes a
+                                single query.  0 (default): adaptive per graph, the
+                                ratio of the measured batched and single-root
+                                traversal times (2 before anything is measured, 16
+                                before a batch is) */
+    int32_t reserved;
 } bfs_serve_config;
 
 /* Defaults: budget 0 (75% of free memory), max_batch 64, 4 streams, queue

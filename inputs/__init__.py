@@ -57,6 +57,8 @@ def _load():
     lib.gg_free.argtypes = [vp]
     lib.gg_pick_roots.restype = i64
     lib.gg_pick_roots.argtypes = [i64, vp, u64, i64, vp]
+    lib.gg_set_verbose.restype = None
+    lib.gg_set_verbose.argtypes = [i32]
     lib.gg_uniform_u64.restype = None
     lib.gg_uniform_u64.argtypes = [u64, u64, i64, vp]
     _lib = lib
@@ -226,7 +228,12 @@ def workload_graph(name: str) -> CSR:
         return erdos_renyi(1 << 20, 4 << 20, ER20_SEED)
     if name.startswith("kron"):
         s = int(name[4:])
-        return kronecker(s, 16, GRAPH_SEED[s])
+        # large graphs take minutes: report each generation phase on stderr
+        _load().gg_set_verbose(1 if s >= 24 else 0)
+        try:
+            return kronecker(s, 16, GRAPH_SEED[s])
+        finally:
+            _load().gg_set_verbose(0)
     raise ValueError(name)
 
 

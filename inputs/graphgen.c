@@ -26,6 +26,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
+#include <stdio.h>
 
 #define GOLDEN 0x9E3779B97F4A7C15ULL
 
@@ -131,9 +132,21 @@ static void gg_free_internal(gg_state *s)
     free(s);
 }
 
+/* Phase messages on stderr for long generations (gg_set_verbose). */
+static int g_verbose = 0;
+void gg_set_verbose(int on) { g_verbose = on; }
+
+static void phase(const char *what, double t0)
+{
+    if (!g_verbose) return;
+    fprintf(stderr, "[graphgen] %s done at %.1f s\n", what, omp_get_wtime() - t0);
+    fflush(stderr);
+}
+
 /* Two passes over the edge stream (count, then fill), then per-row sort+dedup. */
 static gg_state *build(int64_t n, int64_t m, edge_fn fn, void *ctx, int nthreads)
 {
+    const double t0 = omp_get_wtime();
     if (nthreads > 0) omp_set_num_threads(nthreads);
     gg_state *s = (gg_state *)calloc(1, sizeof(gg_state));
     if (!s) return NULL;
@@ -151,6 +164,7 @@ static gg_state *build(int64_t n, int64_t m, edge_fn fn, void *ctx, int nthreads
         __atomic_fetch_add(&cnt[u], 1, __ATOMIC_RELAXED);
         __atomic_fetch_add(&cnt[v], 1, __ATOMIC_RELAXED);
     }
+    phase("degree count pass", t0);
     int64_t acc = 0;
     for (int64_t v = 0; v < n; ++v) { s->off[v] = acc; acc += cnt[v]; cnt[v] = 0; }
     s->off[n] = acc;
@@ -168,6 +182,7 @@ static gg_state *build(int64_t n, int64_t m, edge_fn fn, void *ctx, int nthreads
         s->col[s->off[v] + pv] = u;
     }
 
+    phase("fill pass", t0);
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 1024) reduction(+ : total)
     for (int64_t v = 0; v < n; ++v) {
@@ -181,6 +196,7 @@ static gg_state *build(int64_t n, int64_t m, edge_fn fn, void *ctx, int nthreads
         total += k;
     }
     s->nnz = total;
+    phase("row sort and dedup", t0);
     return s;
 }
 

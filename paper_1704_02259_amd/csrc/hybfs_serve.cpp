@@ -59,8 +59,19 @@ struct Server {
     bool have_first = false;
     Clock::time_point first_submit, last_done;
     long long open = 0;            // queued + running
+    // per graph: running averages of a single-root traversal and of a batched
+    // traversal (host clock around the run); 0 = not measured yet
+    std::vector<double> t_single_us, t_batch_us;
 
     void worker(int i);
+    int batch_threshold(int gid) const
+    {
+        if (cfg.batch_threshold > 0) return cfg.batch_threshold;
+        const double ts = t_single_us[gid], tb = t_batch_us[gid];
+        if (ts <= 0.0) return 2;                  // nothing measured yet: batch what is there
+        if (tb <= 0.0) return 16;
+        return (int)std::min(64.0, std::max(2.0, std::ceil(tb / ts)));
+    }
     int run_group(int i, Graph *g, std::vector<Request *> &rq, double *te_out);
 };
 
@@ -157,8 +168,12 @@ void Server::worker(int i)
             continue;
         }
         Graph *g = graphs[gid];
-        // admission: the traversals in flight may hold at most memory_budget
+        // batch only when the queue is deep enough for one batched traversal
+        // to beat that many single ones; otherwise take one query and leave
+        // the rest to the other slots
         int k = (int)std::min<size_t>(queues[gid].size(), (size_t)cfg.max_batch);
+        if (k > 1 && k < batch_threshold(gid)) k = 1;
+        // admission: the traversals in flight may hold at most memory_budget
         while (k > 1 && used + footprint(g, k, host_out) > cfg.memory_budget) k = std::max(1, k / 2);
         const long long F = footprint(g, k, host_out);
         if (used + F > cfg.memory_budget) {
@@ -204,7 +219,9 @@ void Server::worker(int i)
             else sl.stage_elems = want;
         }
         double te_group = 0.0;
+        const Clock::time_point t_start = Clock::now();
         if (rc == BFS_OK) rc = run_group(i, g, rq, &te_group);
+        const double run_us = std::chrono::duration<double, std::micro>(Clock::now() - t_start).count();
         const std::string err = rc != BFS_OK ? std::string(last_error()) : std::string();
         const Clock::time_point t = Clock::now();
 
@@ -227,6 +244,8 @@ void Server::worker(int i)
         if (rc == BFS_OK) {
             te += te_group;
             last_done = t;
+            double &avg = k == 1 ? t_single_us[gid] : t_batch_us[gid];
+            avg = avg == 0.0 ? run_us : 0.8 * avg + 0.2 * run_us;
         }
         cv_done.notify_all();
     }
@@ -262,6 +281,8 @@ int bfs_serve_create(const bfs_serve_config *cfg_in, bfs_server_t *out)
     if (cfg.out_on_device < 0 || cfg.out_on_device > 1) return set_error(BFS_E_INVALID, "out_on_device is 0 or 1");
     if (cfg.memory_budget < 0 || cfg.alpha < 0 || cfg.beta < 0)
         return set_error(BFS_E_INVALID, "negative memory_budget, alpha or beta");
+    if (cfg.batch_threshold < 0 || cfg.batch_threshold > 64)
+        return set_error(BFS_E_INVALID, "batch_threshold must be in [0, 64]");
     std::unique_ptr<Server> S(new (std::nothrow) Server());
     if (!S) return set_error(BFS_E_NOMEM, "host allocation");
     hipError_t e;
@@ -290,6 +311,8 @@ int bfs_serve_add_graph(bfs_server_t sh, bfs_graph_t g, int32_t *graph_id)
     std::lock_guard<std::mutex> lk(S->mu);
     S->graphs.push_back(reinterpret_cast<Graph *>(g));
     S->queues.emplace_back();
+    S->t_single_us.push_back(0.0);
+    S->t_batch_us.push_back(0.0);
     *graph_id = (int32_t)S->graphs.size() - 1;
     return BFS_OK;
 }

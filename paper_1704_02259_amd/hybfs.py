@@ -68,7 +68,8 @@ class bfs_graph_info(ctypes.Structure):
 class bfs_serve_config(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_int64), ("max_batch", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
-                ("out_on_device", ctypes.c_int32), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32)]
+                ("out_on_device", ctypes.c_int32), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("batch_threshold", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class bfs_serve_report(ctypes.Structure):

@@ -93,7 +93,8 @@ def test_run_batch_rejects_null_graph(lib):
 def test_serve_create_rejects_bad_config(lib):
     from paper_1704_02259_amd import hybfs
     for field, value in (("max_batch", 0), ("max_batch", 65), ("streams", 0), ("streams", 17),
-                         ("queue_capacity", 0), ("out_on_device", 2), ("memory_budget", -1)):
+                         ("queue_capacity", 0), ("out_on_device", 2), ("memory_budget", -1),
+                         ("batch_threshold", -1), ("batch_threshold", 65)):
         cfg = hybfs.bfs_serve_config()
         lib.bfs_serve_config_init(ctypes.byref(cfg))
         setattr(cfg, field, value)

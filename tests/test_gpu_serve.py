@@ -66,7 +66,8 @@ def _alone(torch, G, root):
 
 def test_burst_mix_equals_alone(torch, hyb, graphs):
     gs, Gs = graphs
-    S = hyb.hybfs.Server(streams=4, max_batch=64)
+    # batch whenever two or more queries of a graph are queued
+    S = hyb.hybfs.Server(streams=4, max_batch=64, batch_threshold=2)
     ids = [S.add_graph(G) for G in Gs]
     qs = _queries(gs, 400, 1)
     bufs, tickets = [], []
