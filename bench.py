@@ -72,26 +72,33 @@ def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
     blv = torch.empty((k, g.n), dtype=torch.int32, device=dev)
     bpa = torch.empty((k, g.n), dtype=torch.int32, device=dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    # both sides tuned on the same other roots
+    troots = inputs.pick_roots(g, k, inputs.ROOT_SEED[int(workload[4:])] + 500)
+    sopt, _ = G.autotune(troots[:16], mode="single", max_trials=24, stream=sp)
+    skw = {kk: vv for kk, vv in sopt.items() if kk in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
+                                                       "words_per_wave")}
     # single-root runs (warm-up pass adapts the launch depth), then timed
     te = []
     for i, r in enumerate(roots):
-        _, _, st = G.run(int(r), lv[i], pa[i], stream=sp, stats=True)
+        _, _, st = G.run(int(r), lv[i], pa[i], stream=sp, stats=True, **skw)
         te.append(st["reached_degree_sum"] / 2.0)
     t_single = np.zeros((reps, k))
     for rep in range(reps):
         for i, r in enumerate(roots):
             a, b = ev(), ev()
             a.record(stream)
-            G.run(int(r), lv[i], pa[i], stream=sp, async_=1)
+            G.run(int(r), lv[i], pa[i], stream=sp, async_=1, **skw)
             b.record(stream)
             stream.synchronize()
             t_single[rep, i] = a.elapsed_time(b)
-    G.run_batch(roots, blv, bpa, stream=sp)      # warm-up, adapts the batch depth
+    bopt, brep = G.autotune(troots, mode="batch", max_trials=24, stream=sp)
+    bkw = {kk: vv for kk, vv in bopt.items() if kk in ("alpha", "beta", "grid_blocks", "words_per_wave")}
+    G.run_batch(roots, blv, bpa, stream=sp, **bkw)      # warm-up, adapts the batch depth
     t_batch = []
     for rep in range(reps):
         a, b = ev(), ev()
         a.record(stream)
-        G.run_batch(roots, blv, bpa, stream=sp, async_=1)
+        G.run_batch(roots, blv, bpa, stream=sp, async_=1, **bkw)
         b.record(stream)
         stream.synchronize()
         t_batch.append(a.elapsed_time(b))
@@ -104,7 +111,8 @@ def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
     return {"workload": f"kronecker_scale{workload[4:]}_ef16_{k}roots", "roots": k,
             "sum_single_ms": round(ts, 3), "batch_ms": round(tb, 3), "speedup": round(ts / tb, 3),
             "gteps_batch": round(sum(te) / (tb * 1e-3) / 1e9, 2),
-            "gteps_single_aggregate": round(sum(te) / (ts * 1e-3) / 1e9, 2), "outputs_equal": equal}
+            "gteps_single_aggregate": round(sum(te) / (ts * 1e-3) / 1e9, 2), "outputs_equal": equal,
+            "batch_options": bkw, "single_options": skw, "tune_trials": brep["trials"]}
 
 
 SERVE_GRAPHS = ["kron14", "kron16", "kron18", "kron20", "kron22", "er20"]
@@ -226,6 +234,8 @@ def main():
     ap.add_argument("--beta", type=int, default=0)
     ap.add_argument("--probe-k", type=int, default=-1)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-root leg (SCALE 22)")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default options only")
+    ap.add_argument("--tune-trials", type=int, default=48)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -280,6 +290,18 @@ def main():
 
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
+    tuning = None
+    if not args.no_autotune and not kw:
+        # tune on roots other than the measured ones (a different root seed)
+        s_ = int(args.workload[4:]) if args.workload.startswith("kron") else 20
+        troots = inputs.pick_roots(g, 16, inputs.ROOT_SEED.get(s_, 2020) + 500)
+        t0 = time.time()
+        topt, trep = G.autotune(troots, mode="single", max_trials=args.tune_trials, stream=sp)
+        kw = {k: v for k, v in topt.items() if k in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
+                                                       "words_per_wave")}
+        tuning = {"options": kw, "trials": trep["trials"], "tune_roots": len(troots),
+                  "speedup_on_tune_roots": round(trep["start_us"] / trep["best_us"], 3)}
+        log(f"autotune {time.time() - t0:.1f}s: {tuning}")
     lv = torch.empty(g.n, dtype=torch.int32, device=dev)
     pa = torch.empty(g.n, dtype=torch.int32, device=dev)
 
@@ -313,6 +335,17 @@ def main():
     wall = time.perf_counter() - t_start
     hybfs.bfs_graph_sync(G.handle, sp)
     per_root_ms = np.median(np.array([[a.elapsed_time(b) for a, b in evs[k]] for k in range(K)]), axis=0)
+    default_ms = None
+    if tuning is not None:
+        # the same roots with the default options, for comparison
+        d_ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in roots]
+        for rep in range(2):
+            for i, r in enumerate(roots):
+                d_ev[i][0].record(stream)
+                G.run(int(r), lv, pa, stream=sp, async_=1)
+                d_ev[i][1].record(stream)
+            stream.synchronize()
+        default_ms = np.array([a.elapsed_time(b) for a, b in d_ev])
     ms_per_step = wall * 1000.0 / K
 
     # layer-kernel durations with HIP events around every launch (separate pass)
@@ -370,6 +403,9 @@ def main():
 
     gteps = te / (per_root_ms * 1e-3) / 1e9
     hm = float(len(gteps) / np.sum(1.0 / gteps))
+    if tuning is not None:
+        dg = te / (default_ms * 1e-3) / 1e9
+        tuning["value_default_options"] = round(float(len(dg) / np.sum(1.0 / dg)), 3)
     agg = float(te.sum() / (ms_per_step * 1e-3) / 1e9)
 
     roofline = None
@@ -412,6 +448,7 @@ def main():
         "median_root_us": round(float(np.median(per_root_ms)) * 1e3, 2),
         "min_root_gteps": round(float(gteps.min()), 3),
         "parity_sample_ok": parity_ok,
+        "autotune": tuning,
     }
     if not args.no_batch and args.workload == "kron20":
         log("batched leg (SCALE 22, 64 roots) ...")

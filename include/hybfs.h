@@ -122,9 +122,11 @@ typedef struct bfs_options {
     int32_t probe_k;           /* bottom-up positions tried per vertex before the
                                   wavefront-cooperative scan (MAX_POS of Section
                                   5.2), 0..64 */
-    int32_t small_degree;      /* reserved for the top-down degree split, 1..4096
-                                  (the kernels balance each bitmap word's edges
-                                  over the lanes and do not use it) */
+    int32_t td_hub_degree;     /* top-down degree cut-off, 256..2^24 (default 256):
+                                  a frontier vertex of higher degree is expanded
+                                  through the grid-wide table of its 256-edge
+                                  chunks, one of lower degree together with its
+                                  wavefront's other frontier vertices */
     int32_t grid_blocks;       /* blocks of each layer kernel; 0 = library default */
     int32_t words_per_wave;    /* bitmap words (64 vertices each) one wavefront
                                   task covers: 1, 2, 4, .., 64; 0 = sized from n */
@@ -144,7 +146,7 @@ typedef struct bfs_options {
     void   *stream;            /* hipStream_t to run on; NULL = default stream */
 } bfs_options;
 
-/* Fill defaults: edge rule, alpha 14, beta 24, probe_k 8, small_degree 32,
+/* Fill defaults: edge rule, alpha 14, beta 24, probe_k 8, td_hub_degree 256,
  * automatic grid / words_per_wave / layers_per_launch, host outputs,
  * synchronous, NULL stream. */
 void bfs_options_init(bfs_options *opt);
@@ -224,6 +226,34 @@ int bfs_run(bfs_graph_t g, int32_t root, int32_t *level_out, int32_t *parent_out
  */
 int bfs_run_batch(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t *level_out,
                   int32_t *parent_out, const bfs_options *opt, bfs_stats *stats);
+
+/* ---- autotuning ----
+ * Coordinate descent over the options that change speed but never results:
+ * alpha and beta of the edge rule (Algorithm 3), probe_k (MAX_POS, Section
+ * 5.2), td_hub_degree, words_per_wave and grid_blocks; the last four only
+ * for single-root mode, alpha/beta/words_per_wave/grid_blocks for batches.
+ * Each option set is timed with HIP events on opt->stream: one untimed pass,
+ * then the best of two timed passes over the roots (mode 0: bfs_run of each
+ * root in turn; mode 1: one bfs_run_batch of all k roots).  A candidate
+ * replaces the incumbent only when it is at least 2% faster; descent stops
+ * after a round without improvement, four rounds, or max_trials timings.
+ *   roots, k     the roots to time (host array, each in [0, n)); tuning on
+ *                roots other than those later measured avoids fitting them.
+ *   opt          in: starting options (rule, stream, ...); out: the best set
+ *                found, with the caller's stream / out_on_device / async /
+ *                profile_layers kept.
+ *   report       may be NULL.
+ * Device scratch for the outputs is allocated and freed inside the call.
+ * Errors: BFS_E_INVALID, BFS_E_NOMEM, BFS_E_DEVICE. */
+typedef struct bfs_tune_report {
+    int32_t trials;          /* option sets timed */
+    int32_t rounds;          /* descent rounds */
+    double  start_us;        /* time of one pass with the starting options */
+    double  best_us;         /* time of one pass with the returned options */
+} bfs_tune_report;
+
+int bfs_autotune(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t mode, int32_t max_trials,
+                 bfs_options *opt, bfs_tune_report *report);
 
 /* ---- serving (continuous batching over resident graphs) ----
  *

@@ -79,8 +79,8 @@ struct Params {
     int chunk_log2;                      // top-down hub chunks cover 2^chunk_log2 edges
     const Item *hub;                     // every chunk of every vertex of degree > hub_deg
     long long n_hub;
-    int hub_deg;
-    int small_deg;                       // unused by the kernels (kept for layout)
+    int hub_deg;                         // top-down cut-off of this run (>= the table's)
+    int pad0;
     int probe_k;                         // bottom-up positions tried per lane
     int wpg;                             // bottom-up: bitmap words per wavefront task (1..64)
     int wpg_td;                          // top-down: bitmap words per wavefront task (1..64)

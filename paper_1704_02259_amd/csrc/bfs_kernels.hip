@@ -174,7 +174,9 @@ __device__ void top_down_step(const Params &P, int d, const unsigned long long *
         const long long idx = b0 + (long long)lane * nwaves;
         Item it{-1, 0};
         if (idx < P.n_hub) it = P.hub[idx];
-        const bool hit = it.u >= 0 && test_bit(front, it.u);
+        // the table lists every vertex above the graph's cut-off; a vertex at
+        // or below this run's cut-off was expanded with the flattened edges
+        const bool hit = it.u >= 0 && test_bit(front, it.u) && P.deg[it.u] > P.hub_deg;
         unsigned long long m = __ballot(hit);
         while (m) {
             const int k = __ffsll((long long)m) - 1;

@@ -85,8 +85,9 @@ int validate_options(const bfs_options &o)
         return set_error(BFS_E_INVALID, "unknown rule %d", o.rule);
     if (o.alpha <= 0 || o.beta <= 0) return set_error(BFS_E_INVALID, "alpha and beta must be > 0");
     if (o.probe_k < 0 || o.probe_k > 64) return set_error(BFS_E_INVALID, "probe_k must be in [0, 64]");
-    if (o.small_degree < 1 || o.small_degree > 4096)
-        return set_error(BFS_E_INVALID, "small_degree must be in [1, 4096]");
+    // the flattened expansion sums 64 degrees in 32 bits
+    if (o.td_hub_degree < kHubDegree || o.td_hub_degree > (1 << 24))
+        return set_error(BFS_E_INVALID, "td_hub_degree must be in [%d, 2^24]", kHubDegree);
     if (o.grid_blocks < 0) return set_error(BFS_E_INVALID, "grid_blocks < 0");
     if (o.words_per_wave < 0 || o.words_per_wave > 64 || (o.words_per_wave & (o.words_per_wave - 1)))
         return set_error(BFS_E_INVALID, "words_per_wave must be 0 or a power of two <= 64");
@@ -172,8 +173,7 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->chunk_log2 = kChunkLog2;
     P->hub = g->d_hub;
     P->n_hub = g->n_hub;
-    P->hub_deg = g->hub_deg;
-    P->small_deg = opt.small_degree;
+    P->hub_deg = std::max(g->hub_deg, opt.td_hub_degree);
     P->probe_k = opt.probe_k;
     P->wpg = opt.words_per_wave > 0 ? opt.words_per_wave : g->wpg_default;
     // top-down work is per frontier vertex, so its scan uses wide tasks: a
@@ -324,7 +324,7 @@ void bfs_options_init(bfs_options *opt)
     opt->alpha = 14;
     opt->beta = 24;
     opt->probe_k = 8;
-    opt->small_degree = 32;
+    opt->td_hub_degree = kHubDegree;
 }
 
 int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const int32_t *col_indices,

@@ -34,7 +34,7 @@ RULES = {"edges": 0, "beamer": 0, "table": 1, "td": 2, "bu": 3}
 
 class bfs_options(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
-                ("probe_k", ctypes.c_int32), ("small_degree", ctypes.c_int32),
+                ("probe_k", ctypes.c_int32), ("td_hub_degree", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("words_per_wave", ctypes.c_int32),
                 ("layers_per_launch", ctypes.c_int32), ("out_on_device", ctypes.c_int32),
                 ("async_", ctypes.c_int32), ("profile_layers", ctypes.c_int32),
@@ -80,6 +80,15 @@ class bfs_serve_report(ctypes.Structure):
                                                "gteps")]
 
 
+class bfs_tune_report(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_int32), ("rounds", ctypes.c_int32), ("start_us", ctypes.c_double),
+                ("best_us", ctypes.c_double)]
+
+
+OPTION_KNOBS = ("rule", "alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks", "words_per_wave",
+                "layers_per_launch")
+
+
 class HybfsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"hybfs error {code}: {msg}")
@@ -110,6 +119,8 @@ def load():
         "bfs_run_batch": (ctypes.c_int, [vp, vp, i32, vp, vp, ctypes.POINTER(bfs_options),
                                          ctypes.POINTER(bfs_stats)]),
         "bfs_graph_sync": (ctypes.c_int, [vp, vp]),
+        "bfs_autotune": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.POINTER(bfs_options),
+                                        ctypes.POINTER(bfs_tune_report)]),
         "bfs_serve_config_init": (None, [ctypes.POINTER(bfs_serve_config)]),
         "bfs_serve_create": (ctypes.c_int, [ctypes.POINTER(bfs_serve_config), ctypes.POINTER(vp)]),
         "bfs_serve_add_graph": (ctypes.c_int, [vp, vp, ctypes.POINTER(i32)]),
@@ -257,6 +268,17 @@ class Graph:
                                    "layer_kernel_us": st.layer_kernel_us,
                                    "layers": stats_layers(st, arr)}
         return level, parent
+
+    def autotune(self, roots, mode: str = "single", max_trials: int = 60, stream=None, **kw):
+        """bfs_autotune: returns (options as a dict of keyword arguments for
+        run()/run_batch(), report dict)."""
+        r = np.ascontiguousarray(np.asarray(roots, dtype=np.int32).reshape(-1))
+        opt = bfs_options_init(stream=stream, **kw)
+        rep = bfs_tune_report()
+        _check(load().bfs_autotune(self.handle, r.ctypes.data, len(r), 0 if mode == "single" else 1, max_trials,
+                                   ctypes.byref(opt), ctypes.byref(rep)))
+        return ({k: getattr(opt, k) for k in OPTION_KNOBS},
+                {"trials": rep.trials, "rounds": rep.rounds, "start_us": rep.start_us, "best_us": rep.best_us})
 
     def run_batch(self, roots, level=None, parent=None, stream=None, stats: bool = False, **kw):
         """Batched BFS from every root in `roots` (bfs_run_batch).  Outputs are

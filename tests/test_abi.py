@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_options_defaults(lib):
     from paper_1704_02259_amd import hybfs
     o = hybfs.bfs_options_init()
-    assert (o.rule, o.alpha, o.beta, o.probe_k, o.small_degree) == (0, 14, 24, 8, 32)
+    assert (o.rule, o.alpha, o.beta, o.probe_k, o.td_hub_degree) == (0, 14, 24, 8, 256)
     assert (o.grid_blocks, o.words_per_wave, o.layers_per_launch) == (0, 0, 0)
     assert o.out_on_device == 0 and o.async_ == 0 and not o.stream
 
@@ -113,6 +113,13 @@ def test_serve_calls_reject_null_server(lib):
     assert lib.bfs_serve_poll(None, 1, ctypes.byref(d)) == -1
     assert lib.bfs_serve_wait(None, 1, 0) == -1
     assert lib.bfs_serve_destroy(None) == -1
+
+
+def test_autotune_rejects_null_graph(lib):
+    from paper_1704_02259_amd import hybfs
+    z = np.zeros(4, np.int32)
+    o = hybfs.bfs_options_init()
+    assert lib.bfs_autotune(None, z.ctypes.data, 1, 0, 10, ctypes.byref(o), None) == -1
 
 
 def test_binding_raises_without_library(tmp_path, monkeypatch):

@@ -251,3 +251,14 @@ def test_kron20_batch_64_roots(torch, kron20):
         checks.check_bfs_invariants(g, int(r), lv[i], pa[i], None)
         tot += oracle.reached_degree_sum(g, lv[i])
     assert st["reached_degree_sum"] == tot
+
+
+def test_autotune_batch_keeps_results(torch, kron16):
+    g, G = kron16
+    opts, rep = G.autotune(_kron16_roots(g, 64, 31), mode="batch", max_trials=10)
+    _say("autotune batch", opts, rep)
+    assert 1 <= rep["trials"] <= 10
+    roots = _kron16_roots(g, 64, 32)
+    kw = {k: v for k, v in opts.items() if k != "probe_k"}
+    lv, pa, st = _gpu_batch(torch, G, roots, **kw)
+    _check_rows(g, "kron16", roots, lv, pa)

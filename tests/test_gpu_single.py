@@ -81,13 +81,13 @@ def test_kron16_four_roots(torch, kron16, rule):
         _check_against_oracle(g, int(r), lv, pa, st, rule)
 
 
-@pytest.mark.parametrize("probe_k,small,grid,wpw,layers",
-                         [(0, 1, 0, 0, 0), (1, 4096, 1, 1, 1), (3, 7, 7, 64, 3),
-                          (8, 32, 0, 2, 40), (64, 512, 33, 16, 2)])
-def test_kron16_parameters_do_not_change_output(torch, kron16, probe_k, small, grid, wpw, layers):
+@pytest.mark.parametrize("probe_k,hubdeg,grid,wpw,layers",
+                         [(0, 256, 0, 0, 0), (1, 4096, 1, 1, 1), (3, 257, 7, 64, 3),
+                          (8, 1 << 24, 0, 2, 40), (64, 512, 33, 16, 2)])
+def test_kron16_parameters_do_not_change_output(torch, kron16, probe_k, hubdeg, grid, wpw, layers):
     g, G, roots = kron16
     r = int(roots[0])
-    kw = dict(probe_k=probe_k, small_degree=small, grid_blocks=grid, words_per_wave=wpw,
+    kw = dict(probe_k=probe_k, td_hub_degree=hubdeg, grid_blocks=grid, words_per_wave=wpw,
               layers_per_launch=layers, graph_launch=layers % 2)
     _say("kron16 params", kw)
     lv, pa, st = _gpu_bfs(torch, G, r, **kw)
@@ -269,3 +269,17 @@ def test_async_runs_back_to_back(torch, kron16):
     for r, lv, pa in outs:
         elv, epa = oracle.bfs(g, r)
         assert np.array_equal(lv.cpu().numpy(), elv) and np.array_equal(pa.cpu().numpy(), epa)
+
+
+def test_autotune_single_keeps_results(torch, kron16):
+    """bfs_autotune (single-root mode) on other roots; the options it returns
+    are valid and leave every root's output byte-identical to the oracle."""
+    g, G, roots = kron16
+    tune_roots = inputs.pick_roots(g, 8, 77)
+    opts, rep = G.autotune(tune_roots, mode="single", max_trials=14)
+    _say("autotune single", opts, rep)
+    assert 1 <= rep["trials"] <= 14 and rep["best_us"] <= rep["start_us"] + 1e-9
+    assert opts["td_hub_degree"] >= 256
+    for r in roots:
+        lv, pa, st = _gpu_bfs(torch, G, int(r), **opts)
+        _check_against_oracle(g, int(r), lv, pa)
