@@ -143,6 +143,12 @@ typedef struct bfs_options {
                                   only the root and the output pointers updated per
                                   run; 0 (default): enqueue the kernels one by one
                                   (measured faster on MI355X for this sequence) */
+    int32_t td_binned;         /* large top-down layers bucketed by destination tile
+                                  (parents by LDS minimum, outputs written tile by
+                                  tile): 0 (default) = for graphs of at least 2^23
+                                  vertices, on layers 1..5 with at least 2^22
+                                  frontier edges; 1 = every top-down layer; -1 = never */
+    int32_t reserved2;
     void   *stream;            /* hipStream_t to run on; NULL = default stream */
 } bfs_options;
 

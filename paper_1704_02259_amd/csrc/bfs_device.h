@@ -55,7 +55,7 @@ struct Ctrl {
     int *level;                      // outputs of the current traversal
     int *parent;
     int status;                      // nonzero: a device-side consistency check failed
-    int pad1;
+    int bin_layer;                   // layer whose top-down step runs binned, else -1
     LayerState st[2];
     Slot slot[kSlots];
 };
@@ -95,7 +95,20 @@ struct Params {
     long long alpha, beta;
     int timing;                          // record device timestamps per layer
     int pad1;
+    // binned top-down (large top-down layers): frontier edges are bucketed by
+    // destination tile of 2^bin_log2 vertices, minima taken in LDS per tile
+    int *bin_cnt;                        // [nbins] edges per tile (zero between uses)
+    int *bin_off;                        // [nbins + 1] bucket offsets
+    int *bin_cur;                        // [nbins] bucket fill cursors
+    unsigned long long *bin_pairs;       // [bin_cap] (parent << 32 | vertex within tile)
+    long long bin_cap;
+    long long bin_min_edges;             // smallest m_f that runs binned (when allowed)
+    int nbins;
+    int bin_log2;
 };
+
+constexpr int kBinLog2 = 14;                   // destination tile: 16384 vertices, 64 KiB of minima in LDS
+constexpr int kMaxBins = 4096;
 
 // ---------------------------------------------------------------------------
 // Batched multi-source traversal: lane b of every uint64 mask is root b.
@@ -181,7 +194,11 @@ constexpr int kPullWaves = 4;             // wavefronts per block of the batched
 
 // Launchers (defined in bfs_kernels.hip).
 hipError_t launch_init(const Params &p, int grid, hipStream_t s);
-hipError_t launch_layer(const Params &p, int layer, int grid, hipStream_t s);
+// allow_binned: the three binned kernels follow this layer kernel in the stream
+hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s);
+hipError_t launch_bin_scan(const Params &p, int layer, hipStream_t s);
+hipError_t launch_bin_scatter(const Params &p, int layer, int grid, hipStream_t s);
+hipError_t launch_bin_reduce(const Params &p, int layer, int grid, hipStream_t s);
 hipError_t launch_finish(const Params &p, hipStream_t s);
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);

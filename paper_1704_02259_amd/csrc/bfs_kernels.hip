@@ -101,7 +101,7 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
     }
 }
 
-// Top-down step (Algorithm 1).
+// Top-down edge enumeration (Algorithm 1's two loops).
 //  * A wavefront task covers G bitmap words.  The task's frontier vertices are
 //    laid out over the lanes (64 per round, found by a prefix sum of the
 //    words' popcounts and a select of the set bit), and the edges of those
@@ -111,17 +111,20 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
 //  * Vertices of degree > hub_deg are expanded through the static table of
 //    their 2^chunk_log2-edge chunks, 64 table entries per wavefront step, so a
 //    hub's edges spread over the whole grid.
-__device__ void top_down_step(const Params &P, int d, const unsigned long long *front,
-                              unsigned long long *next, unsigned long long &nf,
-                              unsigned long long &mf, unsigned long long &nh, bool hubs_in_front,
-                              long long gwave, long long nwaves)
+// sink(uq, jq, okq) receives four (source, edge index) pairs per lane, with
+// every lane of the wavefront active; okq marks the real ones.  The
+// assignment of edges to wavefronts depends only on the frontier, so passes
+// over the same frontier see the same edges in the same wavefronts.
+template <class Sink>
+__device__ void td_scan(const Params &P, const unsigned long long *front, bool hubs_in_front, bool fold_vis,
+                        long long gwave, long long nwaves, Sink &sink)
 {
     const int lane = __lane_id();
     const int G = P.wpg_td;
     for (long long base = gwave * G; base < P.W; base += nwaves * G) {
         const long long myw = base + lane;
         const unsigned long long fwl = (lane < G && myw < P.W) ? front[myw] : 0ull;
-        if (fwl) P.vis[myw] |= fwl;              // F_d joins the finished layers (lane owns word)
+        if (fold_vis && fwl) P.vis[myw] |= fwl;  // F_d joins the finished layers (lane owns word)
         const int cnt = __popcll(fwl);
         const int cincl = wave_incl_scan32(cnt);
         const int cex = cincl - cnt;
@@ -161,7 +164,7 @@ __device__ void top_down_step(const Params &P, int d, const unsigned long long *
                     uq[q] = __shfl(u, lo);
                     jq[q] = __shfl(sl, lo) + (idx - __shfl(ex, lo));
                 }
-                td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh);
+                sink(uq, jq, okq);
             }
         }
     }
@@ -195,10 +198,22 @@ __device__ void top_down_step(const Params &P, int d, const unsigned long long *
                     jq[q] = r0 + q * 64 + lane;
                     okq[q] = jq[q] < e;
                 }
-                td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh);
+                sink(uq, jq, okq);
             }
         }
     }
+}
+
+// Top-down step (Algorithm 1) with canonical parents by atomic minimum.
+__device__ void top_down_step(const Params &P, int d, const unsigned long long *front,
+                              unsigned long long *next, unsigned long long &nf,
+                              unsigned long long &mf, unsigned long long &nh, bool hubs_in_front,
+                              long long gwave, long long nwaves)
+{
+    auto sink = [&](const int (&uq)[4], const long long (&jq)[4], const bool (&okq)[4]) {
+        td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh);
+    };
+    td_scan(P, front, hubs_in_front, true, gwave, nwaves, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,6 +410,43 @@ __device__ void flush_counters(unsigned long long nf, unsigned long long mf, uns
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Binned top-down step for large top-down layers.  The frontier's edges
+// (u, v) are bucketed by the destination tile v >> bin_log2, then one block
+// per tile takes each vertex's smallest frontier neighbour with LDS atomics
+// and writes the tile's levels, parents and next-frontier words together.
+// The HBM traffic becomes streaming (rows, bucket writes and reads, tile-wide
+// output runs) instead of one random gather and atomic per edge.  Passes:
+//   count   (in the layer kernel): edges per tile, in an LDS histogram per
+//           block, then one global add per nonzero tile;
+//   scan    (one block): bucket offsets;
+//   scatter: the same edge enumeration (same edges in the same wavefronts),
+//           per-block ranges of each bucket reserved with one atomic per
+//           (block, tile), pairs placed by LDS atomics;
+//   reduce  : per tile, minima in LDS over unvisited targets, then output.
+
+static __device__ void bin_count_pass(const Params &P, const unsigned long long *front, unsigned *hist,
+                                      bool hubs_in_front, long long gwave, long long nwaves)
+{
+    for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    auto sink = [&](const int (&uq)[4], const long long (&jq)[4], const bool (&okq)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!okq[q]) continue;
+            if ((unsigned long long)jq[q] >= (unsigned long long)P.nnz) {
+                atomicOr((unsigned *)&P.ctrl->status, 4u);
+                continue;
+            }
+            atomicAdd(&hist[P.col[jq[q]] >> P.bin_log2], 1u);
+        }
+    };
+    td_scan(P, front, hubs_in_front, true, gwave, nwaves, sink);
+    __syncthreads();
+    for (int b = threadIdx.x; b < P.nbins; b += blockDim.x)
+        if (hist[b]) atomicAdd(&P.bin_cnt[b], (int)hist[b]);
+}
+
 // Control data a block reads at the start of a layer.  It was written by
 // earlier kernels (or, in the finisher, by this block before a barrier), so
 // plain loads see it; thread 0 loads it once and the block shares it.
@@ -409,7 +461,8 @@ struct LayerView {
 
 __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long long nwaves,
                           long long gt, long long nt, bool leader, unsigned long long *s_red,
-                          int nwaves_block, LayerView *view, bool same_kernel, int d_hint)
+                          int nwaves_block, LayerView *view, bool same_kernel, int d_hint,
+                          unsigned *hist, bool allow_binned)
 {
     Ctrl *C = Pin.ctrl;
     if (threadIdx.x == 0) {
@@ -466,7 +519,11 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
         return false;
     }
     const int cur = decide(P, S.dir_prev, n_f, m_f, m_u, v_u);
+    // a large top-down layer is bucketed by destination tile when the three
+    // binned kernels follow this one (every block decides the same)
+    const bool binned = allow_binned && cur == DIR_TD && m_f >= P.bin_min_edges && m_f <= P.bin_cap;
     if (leader) {
+        C->bin_layer = binned ? d : -1;
         if (d < P.trace_cap) {
             LayerRec r;
             r.dir = cur;
@@ -501,7 +558,8 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
     unsigned long long *next = P.bm + (long long)((d + 1) % 3) * P.W;
     unsigned long long *spare = P.bm + (long long)((d + 2) % 3) * P.W;
     unsigned long long nf = 0, mf = 0, nh = 0;
-    if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, view->n_h > 0, gwave, nwaves);
+    if (binned) bin_count_pass(P, front, hist, view->n_h > 0, gwave, nwaves);
+    else if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, view->n_h > 0, gwave, nwaves);
     else bottom_up_step(P, d, front, next, nf, mf, nh, gwave, nwaves);
     for (long long w = gt; w < P.W; w += nt) spare[w] = 0ull;   // `next` of layer d+1
     flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, nwaves_block);
@@ -575,17 +633,18 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
     }
 }
 
-__global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer)
+__global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, int allow_binned)
 {
     const int parity = layer & 1;
     __shared__ unsigned long long s_red[3 * kWavesPerBlock];
     __shared__ LayerView view;
+    __shared__ unsigned hist[kMaxBins];
     const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
     run_layer(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
-              kWavesPerBlock, &view, false, layer);
+              kWavesPerBlock, &view, false, layer, hist, allow_binned != 0 && P.nbins <= kMaxBins);
 }
 
 // One block runs whatever layers remain, with block barriers between them.
@@ -601,10 +660,190 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
         __syncthreads();
         const int parity = s_parity;
         if (!run_layer(P, parity, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, s_red,
-                       kFinishBlock / 64, &view, true, -1))
+                       kFinishBlock / 64, &view, true, -1, nullptr, false))
             break;
         __syncthreads();
     }
+}
+
+// Bucket offsets of a binned layer (one block): exclusive scan of the
+// per-tile counts; the counts are cleared for the next binned layer.
+__global__ void __launch_bounds__(kFinishBlock) bfs_bin_scan_kernel(Params P, int layer)
+{
+    __shared__ int s_part[kFinishBlock];
+    Ctrl *C = P.ctrl;
+    if (C->bin_layer != layer) return;
+    const int per = (P.nbins + kFinishBlock - 1) / kFinishBlock;
+    const int b0 = threadIdx.x * per;
+    int sum = 0;
+    for (int b = b0; b < b0 + per && b < P.nbins; ++b) sum += P.bin_cnt[b];
+    s_part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < kFinishBlock; ++i) {
+            const int t = s_part[i];
+            s_part[i] = acc;
+            acc += t;
+        }
+        P.bin_off[P.nbins] = acc;
+        if ((long long)acc > P.bin_cap) {
+            // cannot happen: the layer was binned only when m_f <= bin_cap
+            atomicOr((unsigned *)&C->status, 64u);
+            C->bin_layer = -2;
+        }
+    }
+    __syncthreads();
+    int acc = s_part[threadIdx.x];
+    for (int b = b0; b < b0 + per && b < P.nbins; ++b) {
+        const int c = P.bin_cnt[b];
+        P.bin_off[b] = acc;
+        P.bin_cur[b] = acc;
+        P.bin_cnt[b] = 0;
+        acc += c;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) bfs_bin_scatter_kernel(Params P, int layer)
+{
+    __shared__ unsigned lbase[kMaxBins];
+    __shared__ int s_go;
+    __shared__ unsigned long long s_hubs;
+    Ctrl *C = P.ctrl;
+    if (threadIdx.x == 0) {
+        s_go = C->bin_layer == layer && P.nbins <= kMaxBins;
+        unsigned long long h = 0;
+        const Slot &sl = C->slot[layer % kSlots];
+        for (int k = 0; k < kSub; ++k) h += sl.c[k][2];
+        s_hubs = h;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
+    const unsigned long long *front = P.bm + (long long)(layer % 3) * P.W;
+    const bool hubs = s_hubs > 0;
+    // this block's edges per tile, then a range of each bucket for them
+    for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) lbase[b] = 0u;
+    __syncthreads();
+    auto count = [&](const int (&uq)[4], const long long (&jq)[4], const bool (&okq)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (okq[q] && (unsigned long long)jq[q] < (unsigned long long)P.nnz)
+                atomicAdd(&lbase[P.col[jq[q]] >> P.bin_log2], 1u);
+    };
+    td_scan(P, front, hubs, false, gwave, nwaves, count);
+    __syncthreads();
+    for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) {
+        const unsigned c = lbase[b];
+        lbase[b] = c ? (unsigned)atomicAdd(&P.bin_cur[b], (int)c) : 0u;
+    }
+    __syncthreads();
+    const unsigned mask = (1u << P.bin_log2) - 1u;
+    auto place = [&](const int (&uq)[4], const long long (&jq)[4], const bool (&okq)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!okq[q] || (unsigned long long)jq[q] >= (unsigned long long)P.nnz) continue;
+            const int v = P.col[jq[q]];
+            const int b = v >> P.bin_log2;
+            const unsigned pos = atomicAdd(&lbase[b], 1u);
+            if ((int)pos < P.bin_off[b + 1])
+                P.bin_pairs[pos] = ((unsigned long long)(unsigned)uq[q] << 32) | (unsigned)(v & mask);
+            else
+                atomicOr((unsigned *)&C->status, 64u);
+        }
+    };
+    td_scan(P, front, hubs, false, gwave, nwaves, place);
+}
+
+// Two blocks of this size and their 64 KiB tiles fit one CU, so one tile's
+// loads overlap another's LDS work.
+constexpr int kReduceBlock = 512;
+
+// One block per destination tile: the smallest frontier neighbour of every
+// unvisited vertex of the tile by LDS atomic minimum over its bucket, then
+// level d+1, parent, next-frontier word and counters, a wavefront per word.
+__global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, int layer)
+{
+    __shared__ unsigned par[1 << kBinLog2];
+    __shared__ unsigned long long visw[(1 << kBinLog2) / 64];
+    __shared__ unsigned long long s_red[3 * (kReduceBlock / 64)];
+    __shared__ int s_go;
+    __shared__ int *s_level;
+    __shared__ int *s_parent;
+    Ctrl *C = P.ctrl;
+    if (threadIdx.x == 0) {
+        s_go = C->bin_layer == layer && P.bin_log2 == kBinLog2;
+        s_level = C->level;
+        s_parent = C->parent;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    int *level = s_level;
+    int *parent = s_parent;
+    const int d = layer;
+    const int lane = __lane_id();
+    const int wib = threadIdx.x >> 6;
+    constexpr int T = 1 << kBinLog2;
+    constexpr int TW = T / 64;
+    unsigned long long *next = P.bm + (long long)((d + 1) % 3) * P.W;
+    unsigned long long nf = 0, mf = 0, nh = 0;
+    for (int tile = blockIdx.x; tile < P.nbins; tile += gridDim.x) {
+        const long long v0 = (long long)tile << kBinLog2;
+        const long long w0 = v0 >> 6;
+        for (int i = threadIdx.x; i < T; i += kReduceBlock) par[i] = 0xFFFFFFFFu;
+        for (int i = threadIdx.x; i < TW; i += kReduceBlock) visw[i] = w0 + i < P.W ? P.vis[w0 + i] : ~0ull;
+        __syncthreads();
+        // four pairs per thread per step, loads first
+        const int e = P.bin_off[tile + 1];
+        for (int i0 = P.bin_off[tile] + threadIdx.x; i0 < e; i0 += 4 * kReduceBlock) {
+            unsigned long long pr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * kReduceBlock;
+                pr[q] = i < e ? P.bin_pairs[i] : ~0ull;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (pr[q] == ~0ull) continue;
+                const unsigned vl = (unsigned)pr[q] & (unsigned)(T - 1);
+                if (!((visw[vl >> 6] >> (vl & 63)) & 1ull)) atomicMin(&par[vl], (unsigned)(pr[q] >> 32));
+            }
+        }
+        __syncthreads();
+        // four words per wavefront per step, their degree loads issued together
+        constexpr int NWB = kReduceBlock / 64;
+        for (int wq = wib; wq < TW; wq += 4 * NWB) {
+            long long v[4];
+            unsigned p[4];
+            bool found[4];
+            int dv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int w = wq + q * NWB;
+                v[q] = v0 + ((long long)w << 6) + lane;
+                p[q] = w < TW ? par[(w << 6) + lane] : 0xFFFFFFFFu;
+                found[q] = p[q] != 0xFFFFFFFFu && v[q] < P.n;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dv[q] = found[q] ? P.deg[v[q]] : 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int w = wq + q * NWB;
+                const unsigned long long um = __ballot(found[q]);
+                if (lane == 0 && um && w0 + w < P.W) next[w0 + w] = um;
+                if (found[q]) {
+                    level[v[q]] = d + 1;
+                    parent[v[q]] = (int)p[q];
+                    nf += 1;
+                    mf += (unsigned long long)dv[q];
+                    nh += dv[q] > P.hub_deg;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, kReduceBlock / 64);
 }
 
 // Isolated-vertex template of the visited bitmap: degree 0 or beyond n.
@@ -627,9 +866,27 @@ hipError_t launch_init(const Params &p, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_layer(const Params &p, int layer, int grid, hipStream_t s)
+hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(bfs_layer_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer);
+    hipLaunchKernelGGL(bfs_layer_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scan(const Params &p, int layer, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_bin_scan_kernel, dim3(1), dim3(kFinishBlock), 0, s, p, layer);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const Params &p, int layer, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_bin_scatter_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_reduce(const Params &p, int layer, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_bin_reduce_kernel, dim3(grid), dim3(kReduceBlock), 0, s, p, layer);
     return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ int validate_options(const bfs_options &o)
         return set_error(BFS_E_INVALID, "words_per_wave must be 0 or a power of two <= 64");
     if (o.layers_per_launch < 0 || o.layers_per_launch > 4096)
         return set_error(BFS_E_INVALID, "layers_per_launch must be in [0, 4096]");
+    if (o.td_binned < -1 || o.td_binned > 1) return set_error(BFS_E_INVALID, "td_binned must be -1, 0 or 1");
     if (o.graph_launch < 0 || o.graph_launch > 1 || o.profile_layers < 0 || o.profile_layers > 1 ||
         o.async < 0 || o.async > 1 || o.out_on_device < 0 || o.out_on_device > 1)
         return set_error(BFS_E_INVALID, "flag options must be 0 or 1");
@@ -103,6 +104,7 @@ int validate_options(const bfs_options &o)
 Workspace::~Workspace()
 {
     if (dbuf) hipFree(dbuf);
+    if (bin_buf) hipFree(bin_buf);
     if (out_tmp) hipFree(out_tmp);
     if (h_ctrl) hipHostFree(h_ctrl);
     if (h_trace) hipHostFree(h_trace);
@@ -157,6 +159,28 @@ int get_workspace(Graph *g, void *stream, Workspace **out)
     return BFS_OK;
 }
 
+// Buckets of the binned top-down step, allocated with the first run that may
+// use them: counts, offsets and cursors per tile, and up to min(nnz, 2^28)
+// (parent, vertex) pairs.
+static int ensure_bins(Graph *g, Workspace *w)
+{
+    if (w->bin_buf) return BFS_OK;
+    const long long cap = std::max<long long>(1, std::min<long long>(g->nnz, 1LL << 28));
+    const size_t a = align256((size_t)(g->nbins + 1) * 4);
+    const size_t bytes = 3 * a + (size_t)cap * 8;
+    hipError_t e;
+    if ((e = hipMalloc(&w->bin_buf, bytes)) != hipSuccess) return hip_fail(e, "binned top-down buckets");
+    char *b = (char *)w->bin_buf;
+    w->bin_cnt = (int *)b;
+    w->bin_off = (int *)(b + a);
+    w->bin_cur = (int *)(b + 2 * a);
+    w->bin_pairs = (unsigned long long *)(b + 3 * a);
+    w->bin_cap = cap;
+    if ((e = hipMemset(w->bin_cnt, 0, a)) != hipSuccess) return hip_fail(e, "bucket init");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "bucket init");
+    return BFS_OK;
+}
+
 // ------------------------------------------------------------------ launch
 void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P)
 {
@@ -188,11 +212,25 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->alpha = opt.alpha;
     P->beta = opt.beta;
     P->timing = opt.profile_layers;
+    P->nbins = g->nbins;
+    P->bin_log2 = kBinLog2;
+    P->bin_cnt = w->bin_cnt;
+    P->bin_off = w->bin_off;
+    P->bin_cur = w->bin_cur;
+    P->bin_pairs = w->bin_pairs;
+    P->bin_cap = w->bin_pairs ? w->bin_cap : 0;
+    P->bin_min_edges = opt.td_binned > 0 ? 1 : (1LL << 22);
 }
 
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
                       hipStream_t s, int *layers_enqueued, bool profile)
 {
+    // binned top-down: allowed on the layers after which its kernels are enqueued
+    const bool bins = g->nbins <= kMaxBins && (opt.td_binned > 0 || (opt.td_binned == 0 && g->bin_auto));
+    if (bins) {
+        const int rc = ensure_bins(g, w);
+        if (rc) return rc;
+    }
     Params P;
     fill_params(g, w, opt, &P);
     P.root = root;
@@ -211,7 +249,14 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     if ((e = launch_init(P, grid, s)) != hipSuccess) return hip_fail(e, "init launch");
     for (int i = 0; i < L; ++i) {
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i], s)) != hipSuccess) return hip_fail(e, "event");
-        if ((e = launch_layer(P, i, grid, s)) != hipSuccess) return hip_fail(e, "layer launch");
+        const int allow = bins && (opt.td_binned > 0 || (i >= 1 && i <= 5));
+        if ((e = launch_layer(P, i, allow, grid, s)) != hipSuccess) return hip_fail(e, "layer launch");
+        if (allow) {
+            if ((e = launch_bin_scan(P, i, s)) != hipSuccess ||
+                (e = launch_bin_scatter(P, i, grid, s)) != hipSuccess ||
+                (e = launch_bin_reduce(P, i, 2 * g->cus, s)) != hipSuccess)
+                return hip_fail(e, "binned top-down launch");
+        }
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i + 1], s)) != hipSuccess) return hip_fail(e, "event");
     }
     if ((e = launch_finish(P, s)) != hipSuccess) return hip_fail(e, "finisher launch");
@@ -231,8 +276,8 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
     char key[160];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k, P.wpg,
-             P.wpg_td, grid, L);
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k, P.wpg,
+             P.wpg_td, P.hub_deg, grid, L);
     hipError_t e;
     auto it = w->replays.find(key);
     if (it == w->replays.end()) {
@@ -255,8 +300,9 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         if ((e = hipGraphAddKernelNode(&R.init, R.graph, nullptr, 0, &kp)) != hipSuccess)
             return hip_fail(e, "graph init node");
         prev = R.init;
+        int no_bins = 0;   // the captured sequence has no binned kernels
         for (int i = 0; i < L; ++i) {
-            void *args[] = {&R.params, &layer_idx[i]};
+            void *args[] = {&R.params, &layer_idx[i], &no_bins};
             kp.func = kernel_ptr_layer();
             kp.kernelParams = args;
             hipGraphNode_t node;
@@ -325,6 +371,7 @@ void bfs_options_init(bfs_options *opt)
     opt->beta = 24;
     opt->probe_k = 8;
     opt->td_hub_degree = kHubDegree;
+    opt->td_binned = 0;
 }
 
 int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const int32_t *col_indices,
@@ -489,6 +536,8 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     const int bper_cu = batch_blocks_per_cu();
     if (bper_cu < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
     g->batch_grid = std::min(bper_cu, 4) * cus;
+    g->nbins = (int)((n + (1LL << kBinLog2) - 1) >> kBinLog2);
+    g->bin_auto = n >= (1LL << 23) && g->nbins <= kMaxBins;
     const int pper_cu = batch_pull_blocks_per_cu();
     if (pper_cu < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
     g->batch_pull_grid = pper_cu * cus;

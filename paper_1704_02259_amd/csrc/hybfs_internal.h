@@ -36,6 +36,11 @@ struct Workspace {
     LayerRec *h_trace = nullptr;  // pinned
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> layer_ev;   // profile_layers: start/end per layer kernel
+    // binned top-down buckets (allocated on first use)
+    void *bin_buf = nullptr;
+    int *bin_cnt = nullptr, *bin_off = nullptr, *bin_cur = nullptr;
+    unsigned long long *bin_pairs = nullptr;
+    long long bin_cap = 0;
     // captured launch sequences: key = option set and layer count
     struct Replay {
         hipGraph_t graph = nullptr;
@@ -99,6 +104,8 @@ struct Graph {
     int wpg_default = 1;
     DepthTracker depth;                  // single-root traversals
     DepthTracker batch_depth;            // batched traversals
+    int nbins = 0;                       // binned top-down: destination tiles
+    bool bin_auto = false;               // binned top-down on by default (large graphs)
     int batch_grid = 0;                  // blocks of the batched push kernel
     int batch_pull_grid = 0;             // blocks of the batched pull kernel (kPullWaves waves each)
     std::mutex mu;

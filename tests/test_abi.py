@@ -42,6 +42,7 @@ def test_options_defaults(lib):
     from paper_1704_02259_amd import hybfs
     o = hybfs.bfs_options_init()
     assert (o.rule, o.alpha, o.beta, o.probe_k, o.td_hub_degree) == (0, 14, 24, 8, 256)
+    assert o.td_binned == 0
     assert (o.grid_blocks, o.words_per_wave, o.layers_per_launch) == (0, 0, 0)
     assert o.out_on_device == 0 and o.async_ == 0 and not o.stream
 

@@ -153,6 +153,20 @@ def test_edge_case_graphs(torch, hyb, case):
     G.close()
 
 
+@pytest.mark.parametrize("case", list(_small_cases()), ids=lambda c: c[0])
+def test_edge_case_graphs_binned_top_down(torch, hyb, case):
+    """Every top-down layer through the binned path (td_binned=1): buckets
+    per destination tile, minima in LDS, tile-wise outputs."""
+    name, g, roots = case
+    G = hyb.Graph.from_csr(g)
+    for rule in ("edges", "td"):
+        for r in roots:
+            _say(name, "binned", rule, r)
+            lv, pa, st = _gpu_bfs(torch, G, r, rule=rule, td_binned=1)
+            _check_against_oracle(g, r, lv, pa, st, rule)
+    G.close()
+
+
 def test_unsorted_rows_duplicates_and_self_loops(torch, hyb):
     base = inputs.kronecker(10)
     rng = np.random.default_rng(1)
@@ -169,6 +183,35 @@ def test_unsorted_rows_duplicates_and_self_loops(torch, hyb):
     for r in inputs.pick_roots(base, 3, 4):
         lv, pa, st = _gpu_bfs(torch, G, int(r))
         _check_against_oracle(base, int(r), lv, pa)
+    G.close()
+
+
+@pytest.mark.parametrize("rule", ["edges", "td"])
+def test_kron16_binned_top_down(torch, kron16, rule):
+    g, G, roots = kron16
+    for r in roots:
+        _say("kron16 binned", rule, int(r))
+        lv, pa, st = _gpu_bfs(torch, G, int(r), rule=rule, td_binned=1)
+        _check_against_oracle(g, int(r), lv, pa, st, rule)
+    # and with the hub cut-off raised, the grid shrunk, several task sizes
+    for kw in (dict(td_hub_degree=4096), dict(grid_blocks=3, words_per_wave=1), dict(td_hub_degree=1024,
+                                                                                     words_per_wave=8)):
+        lv, pa, st = _gpu_bfs(torch, G, int(roots[0]), rule=rule, td_binned=1, **kw)
+        _check_against_oracle(g, int(roots[0]), lv, pa, st, rule)
+
+
+def test_kron18_binned_many_tiles(torch, hyb):
+    """SCALE 18: eight destination tiles; binned on every top-down layer and
+    off entirely give the oracle's result."""
+    g = inputs.kronecker(18)
+    G = hyb.Graph.from_csr(g)
+    for r in inputs.workload_roots("kron18", g, 3):
+        for tb in (1, -1):
+            _say("kron18 binned", tb, int(r))
+            lv, pa, st = _gpu_bfs(torch, G, int(r), td_binned=tb)
+            _check_against_oracle(g, int(r), lv, pa, st)
+        lv, pa, st = _gpu_bfs(torch, G, int(r), rule="td", td_binned=1)
+        _check_against_oracle(g, int(r), lv, pa, st, "td")
     G.close()
 
 
@@ -214,6 +257,14 @@ def test_kron20_sampled_roots_exact(torch, kron20):
     for r in roots[:4]:
         _say("kron20 root", int(r))
         lv, pa, st = _gpu_bfs(torch, G, int(r))
+        _check_against_oracle(g, int(r), lv, pa, st)
+
+
+def test_kron20_binned_top_down(torch, kron20):
+    g, G, roots = kron20
+    for r in roots[:3]:
+        _say("kron20 binned", int(r))
+        lv, pa, st = _gpu_bfs(torch, G, int(r), td_binned=1)
         _check_against_oracle(g, int(r), lv, pa, st)
 
 
