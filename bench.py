@@ -220,6 +220,72 @@ def serving_leg(torch, hybfs, dev, queries=1000, warm=200, pool=96, streams=4, r
     return out
 
 
+def sweep(torch, hybfs, dev, scales=(14, 16, 18, 20, 22), efs=(16, 32, 64), nroots=16):
+    """Harmonic-mean GTEPS over a SCALE x edgefactor grid (the shape of the
+    paper's Figure 3 workload), single-root traversals with default options,
+    16 seeded roots per graph, device outputs."""
+    import inputs
+    rows = []
+    for ef in efs:
+        for sc in scales:
+            t0 = time.time()
+            g = inputs.kronecker(sc, ef, 1000 + sc)
+            roots = inputs.pick_roots(g, nroots, 2000 + sc)
+            G = hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID)
+            stream = torch.cuda.Stream()
+            sp = stream.cuda_stream
+            lv = torch.empty(g.n, dtype=torch.int32, device=dev)
+            pa = torch.empty(g.n, dtype=torch.int32, device=dev)
+            te = []
+            for r in roots:
+                _, _, st = G.run(int(r), lv, pa, stream=sp, stats=True)
+                te.append(st["reached_degree_sum"] / 2.0)
+            t = np.zeros((3, len(roots)))
+            for rep in range(3):
+                for i, r in enumerate(roots):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    G.run(int(r), lv, pa, stream=sp, async_=1)
+                    b.record(stream)
+                    stream.synchronize()
+                    t[rep, i] = a.elapsed_time(b)
+            ms = np.median(t, axis=0)
+            gt = np.array(te) / (ms * 1e-3) / 1e9
+            row = {"scale": sc, "edgefactor": ef, "n": g.n, "nnz": g.nnz, "roots": len(roots),
+                   "hm_gteps": round(float(len(gt) / np.sum(1.0 / gt)), 2),
+                   "median_root_us": round(float(np.median(ms)) * 1e3, 1)}
+            rows.append(row)
+            log(f"sweep {row} ({time.time() - t0:.1f}s)")
+            G.close()
+            del lv, pa
+            torch.cuda.empty_cache()
+    return rows
+
+
+def layer_table(G, g, root, kw, torch, dev):
+    """Per-layer breakdown of one traversal (the analogue of the paper's
+    Tables 4-7): direction, frontier size and edges, HIP-event time of the
+    layer's kernels, the algorithmic bytes of either direction and the
+    achieved algorithmic bandwidth of the direction taken."""
+    import oracle
+    lv = torch.empty(g.n, dtype=torch.int32, device=dev)
+    pa = torch.empty(g.n, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        G.run(int(root), lv, pa, **kw)
+    _, _, st = G.run(int(root), lv, pa, stats=True, profile_layers=1, **kw)
+    elv, _ = oracle.bfs(g, int(root))
+    ab = oracle.algorithmic_bytes(g, elv)
+    rows = []
+    for d, x in enumerate(st["layers"]):
+        td, bu = ab["per_layer"][d] if d < len(ab["per_layer"]) else (0, 0)
+        taken = bu if x["dir"] else td
+        us = x["kernel_us"]
+        rows.append({"layer": d, "dir": "BU" if x["dir"] else "TD", "n_f": x["n_f"], "m_f": x["m_f"],
+                     "m_u": x["m_u"], "us": round(us, 1), "td_bytes": td, "bu_bytes": bu,
+                     "gbs_taken": round(taken / (us * 1e-6) / 1e9, 1) if us > 0 else None})
+    return {"root": int(root), "layers": rows, "total_us": round(st["device_us"], 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +301,10 @@ def main():
     ap.add_argument("--probe-k", type=int, default=-1)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-root leg (SCALE 22)")
     ap.add_argument("--no-autotune", action="store_true", help="time the default options only")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the SCALE 14-22 x edgefactor 16/32/64 sweep (one JSON line)")
+    ap.add_argument("--layer-table", type=int, default=0,
+                    help="also print the per-layer breakdown of this many roots (stderr and JSON)")
     ap.add_argument("--tune-trials", type=int, default=48)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -268,6 +338,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        print(json.dumps({"sweep": sweep(torch, hybfs, dev), "unit": "harmonic-mean GTEPS",
+                          "data": "synthetic"}), flush=True)
+        return
 
     t0 = time.time()
     g = inputs.workload_graph(args.workload)
@@ -450,6 +524,12 @@ def main():
         "parity_sample_ok": parity_ok,
         "autotune": tuning,
     }
+    if args.layer_table:
+        out["layer_table"] = [layer_table(G, g, r, kw, torch, dev) for r in roots[:args.layer_table]]
+        for t in out["layer_table"]:
+            log(f"layer table root {t['root']} ({t['total_us']} us):")
+            for row in t["layers"]:
+                log("  ", row)
     if not args.no_batch and args.workload == "kron20":
         log("batched leg (SCALE 22, 64 roots) ...")
         out["batched"] = batched_leg(torch, hybfs, dev)
