@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--alpha", type=int, default=0)
     ap.add_argument("--beta", type=int, default=0)
     ap.add_argument("--probe-k", type=int, default=-1)
+    ap.add_argument("--first-writer", action="store_true",
+                    help="first-writer top-down parents instead of canonical ones (validated, not compared)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-root leg (SCALE 22)")
     ap.add_argument("--no-autotune", action="store_true", help="time the default options only")
     ap.add_argument("--sweep", action="store_true",
@@ -361,6 +363,8 @@ def main():
         kw["beta"] = args.beta
     if args.probe_k >= 0:
         kw["probe_k"] = args.probe_k
+    if args.first_writer:
+        kw["first_writer"] = 1
 
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream

@@ -148,7 +148,22 @@ typedef struct bfs_options {
                                   tile): 0 (default) = for graphs of at least 2^23
                                   vertices, on layers 1..5 with at least 2^22
                                   frontier edges; 1 = every top-down layer; -1 = never */
-    int32_t reserved2;
+    int32_t first_writer;      /* 1: top-down parents are first-writer-wins (the
+                                  edge that sets a vertex's next-frontier bit
+                                  writes its parent, as Algorithm 1 does): levels
+                                  are unchanged, parents are some neighbour one
+                                  layer closer, no longer the smallest.  Measures
+                                  what canonical parents cost; single-root runs
+                                  only (batches stay canonical).  0 (default):
+                                  canonical parents */
+    int32_t bu_serial_probes;  /* bottom-up phase 1 tests the frontier bits of a
+                                  vertex's leading neighbours one at a time and
+                                  stops at the first hit (1), or all at once to
+                                  overlap their latency (-1); 0 (default): one at
+                                  a time when the frontier bitmap is 2 MiB or more
+                                  (n >= 2^24), where each probe costs a cache line
+                                  of bandwidth */
+    int32_t reserved3;
     void   *stream;            /* hipStream_t to run on; NULL = default stream */
 } bfs_options;
 

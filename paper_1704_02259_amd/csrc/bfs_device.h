@@ -94,7 +94,7 @@ struct Params {
     int rule;
     long long alpha, beta;
     int timing;                          // record device timestamps per layer
-    int pad1;
+    int first_writer;                    // top-down parents by first writer, not minimum
     // binned top-down (large top-down layers): frontier edges are bucketed by
     // destination tile of 2^bin_log2 vertices, minima taken in LDS per tile
     int *bin_cnt;                        // [nbins] edges per tile (zero between uses)
@@ -105,6 +105,8 @@ struct Params {
     long long bin_min_edges;             // smallest m_f that runs binned (when allowed)
     int nbins;
     int bin_log2;
+    int serial_probes;                   // bottom-up: test frontier bits one at a time
+    int pad2;
 };
 
 constexpr int kBinLog2 = 14;                   // destination tile: 16384 vertices, 64 KiB of minima in LDS

@@ -79,6 +79,33 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
             cand[q] = !(((P.vis[w] | front[w]) >> (v[q] & 63)) & 1ull);
         }
     }
+    if (P.first_writer) {
+        // the edge whose atomic OR sets v's next-frontier bit discovers v and
+        // writes its parent (a plain read of the word first skips the atomic
+        // when another edge already did)
+        unsigned long long nw[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nw[q] = cand[q] ? next[v[q] >> 6] : 0ull;
+        unsigned long long ob[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned long long bit = 1ull << (v[q] & 63);
+            cand[q] = cand[q] && !(nw[q] & bit);
+            ob[q] = cand[q] ? atomicOr(&next[v[q] >> 6], bit) : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (cand[q] && !((ob[q] >> (v[q] & 63)) & 1ull)) {
+                P.level[v[q]] = d + 1;
+                P.parent[v[q]] = uq[q];
+                nf += 1;
+                const int dv = P.deg[v[q]];
+                mf += (unsigned long long)dv;
+                nh += dv > P.hub_deg;
+            }
+        }
+        return;
+    }
     unsigned pv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) pv[q] = cand[q] ? (unsigned)P.parent[v[q]] : 0u;
@@ -251,10 +278,17 @@ __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned
             if (b + 3 < e && p0 + 3 < K) c3 = P.col[b + 3];
         }
         bool h0 = false, h1 = false, h2 = false, h3 = false;
-        if (c0 >= 0) h0 = test_bit(front, c0);
-        if (c1 >= 0) h1 = test_bit(front, c1);
-        if (c2 >= 0) h2 = test_bit(front, c2);
-        if (c3 >= 0) h3 = test_bit(front, c3);
+        if (P.serial_probes) {
+            h0 = c0 >= 0 && test_bit(front, c0);
+            h1 = !h0 && c1 >= 0 && test_bit(front, c1);
+            h2 = !h0 && !h1 && c2 >= 0 && test_bit(front, c2);
+            h3 = !h0 && !h1 && !h2 && c3 >= 0 && test_bit(front, c3);
+        } else {
+            if (c0 >= 0) h0 = test_bit(front, c0);
+            if (c1 >= 0) h1 = test_bit(front, c1);
+            if (c2 >= 0) h2 = test_bit(front, c2);
+            if (c3 >= 0) h3 = test_bit(front, c3);
+        }
         if (live) {
             if (h0) { found = true; par = c0; }
             else if (h1) { found = true; par = c1; }
@@ -345,11 +379,21 @@ __device__ void bottom_up_step(const Params &P, int d, const unsigned long long 
             int par[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
+                found[j] = false;
+                par[j] = -1;
+                if (P.serial_probes) {
+                    // one frontier-bit probe at a time, none after the first hit
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+                        if (!found[j] && c[j][p] >= 0 && test_bit(front, c[j][p])) {
+                            found[j] = true;
+                            par[j] = c[j][p];
+                        }
+                    continue;
+                }
                 bool h[4];
 #pragma unroll
                 for (int p = 0; p < 4; ++p) h[p] = c[j][p] >= 0 && test_bit(front, c[j][p]);
-                found[j] = false;
-                par[j] = -1;
 #pragma unroll
                 for (int p = 3; p >= 0; --p)
                     if (h[p]) {

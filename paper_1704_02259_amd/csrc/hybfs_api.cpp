@@ -94,6 +94,9 @@ int validate_options(const bfs_options &o)
     if (o.layers_per_launch < 0 || o.layers_per_launch > 4096)
         return set_error(BFS_E_INVALID, "layers_per_launch must be in [0, 4096]");
     if (o.td_binned < -1 || o.td_binned > 1) return set_error(BFS_E_INVALID, "td_binned must be -1, 0 or 1");
+    if (o.first_writer < 0 || o.first_writer > 1) return set_error(BFS_E_INVALID, "first_writer must be 0 or 1");
+    if (o.bu_serial_probes < -1 || o.bu_serial_probes > 1)
+        return set_error(BFS_E_INVALID, "bu_serial_probes must be -1, 0 or 1");
     if (o.graph_launch < 0 || o.graph_launch > 1 || o.profile_layers < 0 || o.profile_layers > 1 ||
         o.async < 0 || o.async > 1 || o.out_on_device < 0 || o.out_on_device > 1)
         return set_error(BFS_E_INVALID, "flag options must be 0 or 1");
@@ -212,6 +215,8 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->alpha = opt.alpha;
     P->beta = opt.beta;
     P->timing = opt.profile_layers;
+    P->first_writer = opt.first_writer;
+    P->serial_probes = opt.bu_serial_probes > 0 || (opt.bu_serial_probes == 0 && g->n >= (1LL << 24));
     P->nbins = g->nbins;
     P->bin_log2 = kBinLog2;
     P->bin_cnt = w->bin_cnt;
@@ -276,8 +281,8 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
     char key[160];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k, P.wpg,
-             P.wpg_td, P.hub_deg, grid, L);
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k, P.wpg,
+             P.wpg_td, P.hub_deg, P.first_writer, P.serial_probes, grid, L);
     hipError_t e;
     auto it = w->replays.find(key);
     if (it == w->replays.end()) {

@@ -39,7 +39,8 @@ class bfs_options(ctypes.Structure):
                 ("layers_per_launch", ctypes.c_int32), ("out_on_device", ctypes.c_int32),
                 ("async_", ctypes.c_int32), ("profile_layers", ctypes.c_int32),
                 ("graph_launch", ctypes.c_int32), ("td_binned", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("first_writer", ctypes.c_int32), ("bu_serial_probes", ctypes.c_int32),
+                ("reserved3", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class bfs_layer_stat(ctypes.Structure):
@@ -87,7 +88,7 @@ class bfs_tune_report(ctypes.Structure):
 
 
 OPTION_KNOBS = ("rule", "alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks", "words_per_wave",
-                "layers_per_launch", "td_binned")
+                "layers_per_launch", "td_binned", "bu_serial_probes")
 
 
 class HybfsError(RuntimeError):

@@ -67,9 +67,10 @@ def components(g) -> np.ndarray:
 
 
 def check_bfs_invariants(g, root: int, level: np.ndarray, parent: np.ndarray,
-                         comp: np.ndarray | None = None) -> None:
+                         comp: np.ndarray | None = None, canonical: bool = True) -> None:
     """Graph500-style validation plus canonical-parent and component checks.
-    Vectorised over edges (O(n + nnz)); raises AssertionError on failure."""
+    Vectorised over edges (O(n + nnz)); raises AssertionError on failure.
+    canonical=False accepts any neighbour one layer closer as the parent."""
     n = g.n
     level = np.asarray(level)
     parent = np.asarray(parent)
@@ -91,11 +92,18 @@ def check_bfs_invariants(g, root: int, level: np.ndarray, parent: np.ndarray,
         p = parent[others]
         assert np.all((p >= 0) & (p < n))
         assert np.all(level[p] == level[others] - 1)
-        # parent[v] is the minimum over neighbours one layer closer
         closer = both & (level[dst] == level[src] - 1)
-        best = np.full(n, np.iinfo(np.int64).max)
-        np.minimum.at(best, src[closer], dst[closer])
-        assert np.all(best[others] == p)
+        if canonical:
+            # parent[v] is the minimum over neighbours one layer closer
+            best = np.full(n, np.iinfo(np.int64).max)
+            np.minimum.at(best, src[closer], dst[closer])
+            assert np.all(best[others] == p)
+        else:
+            # (v, parent[v]) is an edge of the graph
+            keys = np.sort(src[closer] * n + dst[closer])
+            want = others.astype(np.int64) * n + p.astype(np.int64)
+            pos = np.searchsorted(keys, want)
+            assert np.all((pos < len(keys)) & (keys[np.minimum(pos, len(keys) - 1)] == want))
     # reached set equals the root's connected component
     if comp is not None:
         assert np.array_equal(reached, comp == comp[root])

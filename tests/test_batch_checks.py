@@ -49,3 +49,33 @@ def test_unreachable_vertices_stay_in_m_u():
     u = checks.batch_union_replay(g, [a, b])
     assert u["m_u"].tolist() == [8, 8, 8]
     assert u["n_f"].tolist() == [2, 2, 2]
+
+
+def test_noncanonical_checker_accepts_valid_and_rejects_invalid_trees():
+    """The first-writer validator (check_bfs_invariants(canonical=False)):
+    a grid's tree with the largest closer neighbour as parent is accepted;
+    a parent that is not adjacent, or one at the wrong level, is rejected."""
+    import pytest
+    g = inputs.grid_graph(6, 5)
+    r = 7
+    lv, pa = oracle.bfs(g, r)
+    alt = pa.copy()
+    for v in range(g.n):
+        if lv[v] > 0:
+            row = g.col[g.off[v]:g.off[v + 1]]
+            alt[v] = max(u for u in row if lv[u] == lv[v] - 1)
+    assert not np.array_equal(alt, pa)
+    checks.check_bfs_invariants(g, r, lv, alt, canonical=False)
+    with pytest.raises(AssertionError):
+        checks.check_bfs_invariants(g, r, lv, alt)          # not canonical
+    bad = alt.copy()
+    far = int(np.argmax(lv))
+    bad[far] = r                                            # not adjacent
+    with pytest.raises(AssertionError):
+        checks.check_bfs_invariants(g, r, lv, bad, canonical=False)
+    bad = alt.copy()
+    v = int(np.nonzero(lv == 2)[0][0])
+    row = g.col[g.off[v]:g.off[v + 1]]
+    bad[v] = int(next(u for u in row if lv[u] == 3))        # adjacent, one layer further
+    with pytest.raises(AssertionError):
+        checks.check_bfs_invariants(g, r, lv, bad, canonical=False)

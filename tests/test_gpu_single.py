@@ -88,6 +88,7 @@ def test_kron16_parameters_do_not_change_output(torch, kron16, probe_k, hubdeg, 
     g, G, roots = kron16
     r = int(roots[0])
     kw = dict(probe_k=probe_k, td_hub_degree=hubdeg, grid_blocks=grid, words_per_wave=wpw,
+              bu_serial_probes=1 if probe_k % 2 else -1,
               layers_per_launch=layers, graph_launch=layers % 2)
     _say("kron16 params", kw)
     lv, pa, st = _gpu_bfs(torch, G, r, **kw)
@@ -195,7 +196,8 @@ def test_kron16_binned_top_down(torch, kron16, rule):
         _check_against_oracle(g, int(r), lv, pa, st, rule)
     # and with the hub cut-off raised, the grid shrunk, several task sizes
     for kw in (dict(td_hub_degree=4096), dict(grid_blocks=3, words_per_wave=1), dict(td_hub_degree=1024,
-                                                                                     words_per_wave=8)):
+                                                                                     words_per_wave=8),
+               dict(bu_serial_probes=1), dict(bu_serial_probes=1, probe_k=16)):
         lv, pa, st = _gpu_bfs(torch, G, int(roots[0]), rule=rule, td_binned=1, **kw)
         _check_against_oracle(g, int(roots[0]), lv, pa, st, rule)
 
@@ -334,3 +336,30 @@ def test_autotune_single_keeps_results(torch, kron16):
     for r in roots:
         lv, pa, st = _gpu_bfs(torch, G, int(r), **opts)
         _check_against_oracle(g, int(r), lv, pa)
+
+
+@pytest.mark.parametrize("rule", ["edges", "td"])
+def test_first_writer_parents(torch, kron16, hyb, rule):
+    """first_writer=1 (Algorithm 1's first-writer parents): levels and layer
+    counters still equal the oracle's; parents are valid BFS-tree parents
+    (a neighbour one layer closer), checked by the invariants."""
+    g, G, roots = kron16
+    for r in roots:
+        lv, pa, st = _gpu_bfs(torch, G, int(r), rule=rule, first_writer=1)
+        elv, _ = oracle.bfs(g, int(r))
+        assert np.array_equal(lv, elv)
+        checks.check_bfs_invariants(g, int(r), lv, pa, canonical=False)
+        rep = oracle.layer_replay(g, elv)
+        assert [x["n_f"] for x in st["layers"]] == rep["n_f"].tolist()
+    for name, gg, rr in list(_small_cases())[:8]:
+        GG = hyb.Graph.from_csr(gg)
+        for r in rr:
+            lv, pa, st = _gpu_bfs(torch, GG, r, rule="td", first_writer=1)
+            assert np.array_equal(lv, oracle.bfs(gg, r)[0]), name
+            checks.check_bfs_invariants(gg, r, lv, pa, canonical=False)
+        GG.close()
+    # the captured launch sequence keys on the parent mode
+    lv, pa, _ = _gpu_bfs(torch, G, int(roots[0]), graph_launch=1, first_writer=1)
+    checks.check_bfs_invariants(g, int(roots[0]), lv, pa, canonical=False)
+    lv, pa, _ = _gpu_bfs(torch, G, int(roots[0]), graph_launch=1)
+    _check_against_oracle(g, int(roots[0]), lv, pa)
