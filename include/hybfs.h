@@ -52,7 +52,9 @@ typedef struct bfs_graph *bfs_graph_t;
 /* ---- graph creation flags ---- */
 #define BFS_GRAPH_DEVICE_INPUT   1u  /* row_offsets / col_indices are device pointers */
 #define BFS_GRAPH_ASSUME_VALID   2u  /* skip the host-side structural checks */
-#define BFS_GRAPH_CHECK_SYMMETRY 4u  /* also verify that every edge is stored both ways */
+#define BFS_GRAPH_CHECK_SYMMETRY 4u  /* also verify that every edge is stored both ways
+                                        (runs the structural checks too, even with
+                                        BFS_GRAPH_ASSUME_VALID) */
 #define BFS_GRAPH_SORT_ROWS      8u  /* rows may be unsorted: sort the library's copy */
 
 /*

@@ -405,7 +405,7 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     if (dev_in) {
         try {
             h_off_store.resize((size_t)n + 1);
-            if (validate || sort_rows) h_col_store.resize((size_t)nnz);
+            if (validate || sort_rows || symmetry) h_col_store.resize((size_t)nnz);
         } catch (...) {
             return set_error(BFS_E_NOMEM, "host staging");
         }
@@ -435,7 +435,8 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
             std::sort(h_col_store.begin() + h_off[v], h_col_store.begin() + h_off[v + 1]);
         h_col = h_col_store.empty() ? nullptr : h_col_store.data();
     }
-    if (validate) {
+    // a symmetry check needs in-range, sorted rows: it implies the full check
+    if (validate || symmetry) {
         int rc = check_csr(n, nnz, h_off, h_col, true, symmetry);
         if (rc) return rc;
     }

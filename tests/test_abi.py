@@ -75,6 +75,9 @@ def test_graph_create_rejects_bad_csr_on_host(lib):
     col4 = np.array([1], np.int32)
     rc, msg = _create(lib, 2, 1, off4, col4, flags=4)
     assert rc == -1 and "reverse" in msg
+    # ... also when the structural checks are otherwise skipped
+    rc, msg = _create(lib, 2, 1, off4, col4, flags=4 | 2)
+    assert rc == -1 and "reverse" in msg
     rc, msg = _create(lib, 2, 2, off, col, flags=1 << 10)
     assert rc == -1 and "flag" in msg
 
