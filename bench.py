@@ -498,7 +498,7 @@ def main():
         traffic = measured_traffic(args.workload)
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                    "kernel": "bfs_layer_kernel", "launches": launches_b,
+                    "kernel": "bfs_layer_kernel (layer 0: bfs_root_kernel)", "launches": launches_b,
                     "alg_bytes_per_launch": round(bytes_per_launch, 1), "avg_launch_us": round(avg_us, 3),
                     "traversal_frac": round(sum(balg_total) / (traversal_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}
 

@@ -197,7 +197,9 @@ typedef struct bfs_stats {
                                    half of it is the TEPS numerator (Section 6.3) */
     double  device_us;       /* out: HIP-event time of the whole traversal */
     int32_t layer_launches;  /* out: layer kernels enqueued (some may find the
-                                traversal already finished) */
+                                traversal already finished); layer 0 of a
+                                root of degree <= 4096 is a one-block kernel
+                                and counts as one of them */
     int32_t reserved;
     double  layer_kernel_us; /* out: sum of the HIP-event durations of all layer
                                 kernels (profile_layers), else 0 */

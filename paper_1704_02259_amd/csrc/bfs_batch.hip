@@ -537,7 +537,6 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
             r.m_f = view->c[2];
             r.m_u = m_u;
             r.v_u = -1;
-            r.t = 0;
             P.trace[d] = r;
         }
     }

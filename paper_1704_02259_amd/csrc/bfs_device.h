@@ -41,7 +41,6 @@ struct LayerRec {
     int dir;
     int pad;
     long long n_f, m_f, m_u, v_u;
-    unsigned long long t;            // device wall clock when the layer started
 };
 
 struct Ctrl {
@@ -51,7 +50,6 @@ struct Ctrl {
     int root;
     long long reached;
     long long reached_deg;
-    unsigned long long t_end;
     int *level;                      // outputs of the current traversal
     int *parent;
     int status;                      // nonzero: a device-side consistency check failed
@@ -93,7 +91,7 @@ struct Params {
     int root;
     int rule;
     long long alpha, beta;
-    int timing;                          // record device timestamps per layer
+    int pad1;
     int first_writer;                    // top-down parents by first writer, not minimum
     // binned top-down (large top-down layers): frontier edges are bucketed by
     // destination tile of 2^bin_log2 vertices, minima taken in LDS per tile
@@ -202,6 +200,9 @@ hipError_t launch_bin_scan(const Params &p, int layer, hipStream_t s);
 hipError_t launch_bin_scatter(const Params &p, int layer, int grid, hipStream_t s);
 hipError_t launch_bin_reduce(const Params &p, int layer, int grid, hipStream_t s);
 hipError_t launch_finish(const Params &p, hipStream_t s);
+// layer 0 in one block (roots of small degree; see kRootKernelDegree)
+hipError_t launch_root(const Params &p, hipStream_t s);
+constexpr long long kRootKernelDegree = 4096;
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);
 void *kernel_ptr_init();

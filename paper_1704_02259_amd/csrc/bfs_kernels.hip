@@ -557,7 +557,6 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
             C->nlayers = d;
             C->reached = S.reached;
             C->reached_deg = S.reached_deg;
-            C->t_end = 0ull;
             C->done = 1;
         }
         return false;
@@ -576,10 +575,10 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
             r.m_f = m_f;
             r.m_u = m_u;
             r.v_u = v_u;
-            // no device clock read here: a kernel that merely contains one
-            // (even on a branch not taken) was measured about 10 us slower per
-            // launch on gfx950; per-layer times come from HIP events instead
-            r.t = 0ull;
+            // no device clock is read anywhere in these kernels: a kernel that
+            // merely contains one (even on a branch not taken) was measured
+            // about 10 us slower per launch on gfx950; per-layer times come
+            // from HIP events around the launches instead
             P.trace[d] = r;
         }
         LayerState Nx = S;
@@ -656,7 +655,6 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
         C->parity = 0;
         C->reached = 0;
         C->reached_deg = 0;
-        C->t_end = 0;
         LayerState S;
         S.d = 0;
         S.dir_prev = DIR_TD;                 // Algorithm 3 starts top-down
@@ -890,6 +888,65 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
     flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, kReduceBlock / 64);
 }
 
+// Layer 0 in one block, for a root of small degree: F_0 = {root}, so the
+// top-down step is the expansion of the root's own row (each neighbour's
+// parent is the root; duplicates are settled by the next-frontier bit), and a
+// whole-grid launch would spend its time on launch and a bitmap scan.  The
+// direction Algorithm 3 picks for layer 0 is recorded as usual; a bottom-up
+// step from {root} would find exactly the same vertices and parents.
+__global__ void __launch_bounds__(kFinishBlock) bfs_root_kernel(Params P)
+{
+    __shared__ unsigned long long s_red[3 * (kFinishBlock / 64)];
+    Ctrl *C = P.ctrl;
+    const int root = P.root;
+    const long long s0 = P.off[root], e0 = P.off[root + 1];
+    const long long deg_r = e0 - s0;
+    if (threadIdx.x == 0) {
+        const LayerState S = C->st[0];
+        const long long m_u = S.m_u - deg_r, v_u = S.v_u - 1;
+        const int cur = decide(P, S.dir_prev, 1, deg_r, m_u, v_u);
+        C->bin_layer = -1;
+        if (P.trace_cap > 0) {
+            LayerRec r;
+            r.dir = cur;
+            r.pad = 0;
+            r.n_f = 1;
+            r.m_f = deg_r;
+            r.m_u = m_u;
+            r.v_u = v_u;
+            P.trace[0] = r;
+        }
+        LayerState Nx = S;
+        Nx.d = 1;
+        Nx.dir_prev = cur;
+        Nx.m_u = m_u;
+        Nx.v_u = v_u;
+        Nx.reached = 1;
+        Nx.reached_deg = deg_r;
+        C->st[1] = Nx;
+        C->parity = 1;
+        P.vis[root >> 6] |= 1ull << (root & 63);      // F_0 joins the finished layers
+    }
+    for (long long w = threadIdx.x; w < P.W; w += kFinishBlock) P.bm[2 * P.W + w] = 0ull;   // `next` of layer 1
+    unsigned long long *next = P.bm + P.W;
+    unsigned long long nf = 0, mf = 0, nh = 0;
+    for (long long j = s0 + threadIdx.x; j < e0; j += kFinishBlock) {
+        const int v = P.col[j];
+        if (v == root || (unsigned)v >= (unsigned)P.n) continue;
+        const unsigned long long bit = 1ull << (v & 63);
+        const unsigned long long old = atomicOr(&next[v >> 6], bit);
+        if (!(old & bit)) {
+            P.level[v] = 1;
+            P.parent[v] = root;
+            const int dv = P.deg[v];
+            nf += 1;
+            mf += (unsigned long long)dv;
+            nh += dv > P.hub_deg;
+        }
+    }
+    flush_counters(nf, mf, nh, &C->slot[1], s_red, kFinishBlock / 64);
+}
+
 // Isolated-vertex template of the visited bitmap: degree 0 or beyond n.
 __global__ void iso_template_kernel(const long long *off, long long n, long long W,
                                     unsigned long long *iso)
@@ -931,6 +988,12 @@ hipError_t launch_bin_scatter(const Params &p, int layer, int grid, hipStream_t 
 hipError_t launch_bin_reduce(const Params &p, int layer, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(bfs_bin_reduce_kernel, dim3(grid), dim3(kReduceBlock), 0, s, p, layer);
+    return hipGetLastError();
+}
+
+hipError_t launch_root(const Params &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_root_kernel, dim3(1), dim3(kFinishBlock), 0, s, p);
     return hipGetLastError();
 }
 

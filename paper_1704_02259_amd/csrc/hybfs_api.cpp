@@ -214,7 +214,6 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->rule = opt.rule;
     P->alpha = opt.alpha;
     P->beta = opt.beta;
-    P->timing = opt.profile_layers;
     P->first_writer = opt.first_writer;
     P->serial_probes = opt.bu_serial_probes > 0 || (opt.bu_serial_probes == 0 && g->n >= (1LL << 24));
     P->nbins = g->nbins;
@@ -254,6 +253,12 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     if ((e = launch_init(P, grid, s)) != hipSuccess) return hip_fail(e, "init launch");
     for (int i = 0; i < L; ++i) {
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i], s)) != hipSuccess) return hip_fail(e, "event");
+        if (i == 0 && g->h_deg[root] <= kRootKernelDegree) {
+            // layer 0 is the root's own row: one block instead of the grid
+            if ((e = launch_root(P, s)) != hipSuccess) return hip_fail(e, "root launch");
+            if (profile && (e = hipEventRecord(w->layer_ev[1], s)) != hipSuccess) return hip_fail(e, "event");
+            continue;
+        }
         const int allow = bins && (opt.td_binned > 0 || (i >= 1 && i <= 5));
         if ((e = launch_layer(P, i, allow, grid, s)) != hipSuccess) return hip_fail(e, "layer launch");
         if (allow) {
@@ -518,6 +523,7 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     }
     if ((e = hipMemcpy(g->d_deg, deg.data(), n * 4, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "upload degrees");
+    g->h_deg = std::move(deg);
     if ((e = hipMemcpy(g->d_slab, slab.data(), n * 4 * g->slab_k, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "upload slab");
     if ((e = launch_iso_template(g->d_off, n, g->W, g->d_iso, 0)) != hipSuccess) return hip_fail(e, "iso kernel");

@@ -98,6 +98,7 @@ struct Graph {
     long long n_hub = 0;
     int hub_deg = 0;
     long long isolated = 0, max_degree = 0;
+    std::vector<int32_t> h_deg;   // host copy of the degrees (launch choices)
     int cus = 0;
     int blocks_per_cu = 0;
     int grid_default = 0;

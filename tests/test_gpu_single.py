@@ -363,3 +363,20 @@ def test_first_writer_parents(torch, kron16, hyb, rule):
     checks.check_bfs_invariants(g, int(roots[0]), lv, pa, canonical=False)
     lv, pa, _ = _gpu_bfs(torch, G, int(roots[0]), graph_launch=1)
     _check_against_oracle(g, int(roots[0]), lv, pa)
+
+
+def test_root_degree_paths(torch, kron16, hyb):
+    """Layer 0 runs in one block for roots of degree <= 4096 and in the grid
+    kernel above that: the highest-degree vertex, a degree-4096-ish vertex and
+    a leaf all give the oracle's output and per-layer counters."""
+    g, G, _ = kron16
+    deg = np.diff(g.off)
+    order = np.argsort(deg)
+    picks = [int(order[-1]), int(order[np.searchsorted(deg[order], 4096, side="right") - 1]),
+             int(order[np.searchsorted(deg[order], 1)])]
+    for r in picks:
+        _say("root degree", int(deg[r]))
+        lv, pa, st = _gpu_bfs(torch, G, r)
+        _check_against_oracle(g, r, lv, pa, st)
+        lv, pa, st = _gpu_bfs(torch, G, r, rule="bu")
+        _check_against_oracle(g, r, lv, pa, st, "bu")
