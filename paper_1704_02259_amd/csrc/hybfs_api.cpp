@@ -144,8 +144,12 @@ int get_workspace(Graph *g, void *stream, Workspace **out)
     if ((e = hipHostMalloc((void **)&w->h_trace, kTraceCap * sizeof(LayerRec), hipHostMallocDefault)) !=
         hipSuccess)
         return hip_fail(e, "pinned trace");
-    if ((e = hipEventCreate(&w->e0)) != hipSuccess) return hip_fail(e, "event");
-    if ((e = hipEventCreate(&w->e1)) != hipSuccess) return hip_fail(e, "event");
+    // timing-only events (read after a stream synchronize): recorded without
+    // a system-scope fence, so no cache write-back and invalidate lands in
+    // the window they measure
+    if ((e = hipEventCreateWithFlags(&w->e0, hipEventDisableSystemFence)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&w->e1, hipEventDisableSystemFence)) != hipSuccess)
+        return hip_fail(e, "event");
     const long long W = g->W;
     w->bytes = workspace_bytes(W);
     if ((e = hipMalloc(&w->dbuf, w->bytes)) != hipSuccess) return hip_fail(e, "workspace allocation");
@@ -246,7 +250,8 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     if (profile) {
         while ((int)w->layer_ev.size() < 2 * L) {
             hipEvent_t ev;
-            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "event");
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence)) != hipSuccess)
+                return hip_fail(e, "event");
             w->layer_ev.push_back(ev);
         }
     }
@@ -643,13 +648,15 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
 
     const bool profile = opt.profile_layers && stats && !opt.async;
     int launched = 0;
-    if ((e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
+    // the traversal's own events only serve stats->device_us: every event
+    // record is a marker packet with its own cost on the device
+    if (stats && (e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
     if (!opt.graph_launch || profile)
         rc = enqueue_traversal(g, w, opt, root, lvl, par, s, &launched, profile);
     else
         rc = enqueue_traversal_graph(g, w, opt, root, lvl, par, s, &launched);
     if (rc) return rc;
-    if ((e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
+    if (stats && (e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
     if (opt.async) return BFS_OK;
 
     if ((e = hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) != hipSuccess)

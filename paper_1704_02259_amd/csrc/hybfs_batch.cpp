@@ -42,8 +42,9 @@ int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
     if ((e = hipHostMalloc((void **)&w->h_trace, kTraceCap * sizeof(LayerRec), hipHostMallocDefault)) !=
         hipSuccess)
         return hip_fail(e, "pinned trace");
-    if ((e = hipEventCreate(&w->e0)) != hipSuccess) return hip_fail(e, "event");
-    if ((e = hipEventCreate(&w->e1)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreateWithFlags(&w->e0, hipEventDisableSystemFence)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&w->e1, hipEventDisableSystemFence)) != hipSuccess)
+        return hip_fail(e, "event");
     const long long n = g->n, W = g->W;
     w->bytes = batch_workspace_bytes(n, W);
     if ((e = hipMalloc(&w->dbuf, w->bytes)) != hipSuccess) return hip_fail(e, "batch workspace allocation");
@@ -109,7 +110,8 @@ int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int
     if (profile) {
         while ((int)w->layer_ev.size() < 2 * L) {
             hipEvent_t ev;
-            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "event");
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence)) != hipSuccess)
+                return hip_fail(e, "event");
             w->layer_ev.push_back(ev);
         }
     }
@@ -194,7 +196,7 @@ int bfs_run_batch(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t *leve
         int *lvl = opt.out_on_device ? level_out + (long long)g0 * n : stage;
         int *par = opt.out_on_device ? parent_out + (long long)g0 * n : stage + (long long)kg * n;
         int launched = 0;
-        if ((e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
+        if (stats && (e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
         LanePtrs out;
         for (int b = 0; b < kLanes; ++b) {
             out.level[b] = b < kg ? lvl + (long long)b * n : nullptr;
@@ -202,7 +204,7 @@ int bfs_run_batch(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t *leve
         }
         rc = enqueue_batch(g, w, opt, roots + g0, kg, out, s, profile, &launched);
         if (rc) return rc;
-        if ((e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
+        if (stats && (e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
         if (opt.async) continue;
 
         if ((e = hipMemcpyAsync(w->h_ctrl, w->ctrl, sizeof(BCtrl), hipMemcpyDeviceToHost, s)) != hipSuccess)

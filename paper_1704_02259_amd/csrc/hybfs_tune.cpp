@@ -113,7 +113,9 @@ int bfs_autotune(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t mode, 
     hipError_t e;
     const long long outs = mode == 0 ? 2 * g->n : 2LL * k * g->n;
     if ((e = hipMalloc(&T.out, outs * 4)) != hipSuccess) return hip_fail(e, "tuning outputs");
-    if ((e = hipEventCreate(&T.e0)) != hipSuccess || (e = hipEventCreate(&T.e1)) != hipSuccess)
+    // timing-only events: no system-scope fence inside the measured window
+    if ((e = hipEventCreateWithFlags(&T.e0, hipEventDisableSystemFence)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&T.e1, hipEventDisableSystemFence)) != hipSuccess)
         return hip_fail(e, "event");
 
     const int grid0 = mode == 0 ? g->grid_default : g->batch_grid;
