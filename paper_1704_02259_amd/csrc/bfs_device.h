@@ -203,6 +203,10 @@ hipError_t launch_finish(const Params &p, hipStream_t s);
 // layer 0 in one block (roots of small degree; see kRootKernelDegree)
 hipError_t launch_root(const Params &p, hipStream_t s);
 constexpr long long kRootKernelDegree = 4096;
+// initialisation and layer 0 in one grid-wide kernel: block b owns `per`
+// bitmap words (at most kFuseWords); needs every counter slot at zero
+hipError_t launch_init_root(const Params &p, int grid, int per, hipStream_t s);
+constexpr int kFuseWords = 1024;
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);
 void *kernel_ptr_init();

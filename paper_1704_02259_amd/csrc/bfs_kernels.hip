@@ -706,6 +706,12 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
             break;
         __syncthreads();
     }
+    // the traversal is over: leave every counter slot at zero, so that the
+    // next traversal on this workspace may add layer-1 counts in its first kernel
+    __syncthreads();
+    unsigned long long *c = &P.ctrl->slot[0].c[0][0];
+    constexpr int kCounters = (int)(sizeof(Slot) / sizeof(unsigned long long)) * kSlots;
+    for (int i = threadIdx.x; i < kCounters; i += kFinishBlock) c[i] = 0ull;
 }
 
 // Bucket offsets of a binned layer (one block): exclusive scan of the
@@ -894,6 +900,122 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
 // whole-grid launch would spend its time on launch and a bitmap scan.  The
 // direction Algorithm 3 picks for layer 0 is recorded as usual; a bottom-up
 // step from {root} would find exactly the same vertices and parents.
+// Per-BFS initialisation fused with layer 0, for a root of degree at most
+// kRootKernelDegree.  Block b owns bitmap words [b*per, (b+1)*per) and their
+// vertices: it writes their initial outputs and bitmap words, then takes the
+// root's neighbours that fall in its range (every block reads the root's
+// row), so each output entry and bitmap word is written by one block only
+// and no ordering between blocks is needed.  Layer 1's counters are added
+// here; they start at zero because the previous traversal's finisher cleared
+// them, and the host uses this kernel only when that holds.
+__global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per)
+{
+    __shared__ unsigned long long s_next[kFuseWords];
+    __shared__ unsigned long long s_red[3 * kWavesPerBlock];
+    Ctrl *C = P.ctrl;
+    const int root = P.root;
+    const long long rw = root >> 6;
+    const unsigned long long rbit = 1ull << (root & 63);
+    const long long s0 = P.off[root], e0 = P.off[root + 1];
+    const long long deg_r = e0 - s0;
+    const long long w0 = min((long long)blockIdx.x * per, P.W);
+    const long long w1 = min(w0 + per, P.W);
+    const long long v0 = w0 << 6, v1 = min(w1 << 6, P.n);
+    for (long long w = w0 + threadIdx.x; w < w1; w += kBlock) {
+        const unsigned long long rb = (w == rw) ? rbit : 0ull;
+        s_next[w - w0] = 0ull;
+        P.vis[w] = P.iso[w] | rb;            // F_0 = {root} is finished after layer 0
+        P.bm[w] = rb;
+        P.bm[2 * P.W + w] = 0ull;            // `next` of layer 1
+    }
+    if (v0 < v1) {
+        // outputs of the range: 16-byte stores when both arrays are 16-byte
+        // aligned (v0 is a multiple of 64, so the range keeps the alignment);
+        // a block past the last word owns nothing and writes nothing
+        const bool vec = ((((unsigned long long)P.level) | ((unsigned long long)P.parent)) & 15ull) == 0;
+        const long long q1 = vec ? (v1 >> 2) : (v0 >> 2);
+        int4 *l4 = (int4 *)P.level;
+        int4 *p4 = (int4 *)P.parent;
+        for (long long q = (v0 >> 2) + threadIdx.x; q < q1; q += kBlock) {
+            int4 a = make_int4(-1, -1, -1, -1), b = a;
+            if (q == (root >> 2)) {
+                const int c = root & 3;
+                if (c == 0) { a.x = 0; b.x = root; }
+                if (c == 1) { a.y = 0; b.y = root; }
+                if (c == 2) { a.z = 0; b.z = root; }
+                if (c == 3) { a.w = 0; b.w = root; }
+            }
+            l4[q] = a;
+            p4[q] = b;
+        }
+        for (long long v = (q1 << 2) + threadIdx.x; v < v1; v += kBlock) {
+            P.level[v] = v == root ? 0 : -1;
+            P.parent[v] = v == root ? root : -1;
+        }
+    }
+    __syncthreads();   // the range's -1 entries precede its layer-1 entries
+    unsigned long long nf = 0, mf = 0, nh = 0;
+    for (long long j = s0 + threadIdx.x; j < e0; j += kBlock) {
+        const int v = P.col[j];
+        if (v == root || v < v0 || v >= v1) continue;
+        const unsigned long long bit = 1ull << (v & 63);
+        const unsigned long long old = atomicOr(&s_next[(v >> 6) - w0], bit);   // LDS: repeated entries count once
+        if (!(old & bit)) {
+            P.level[v] = 1;
+            P.parent[v] = root;
+            const int dv = P.deg[v];
+            nf += 1;
+            mf += (unsigned long long)dv;
+            nh += dv > P.hub_deg;
+        }
+    }
+    __syncthreads();
+    for (long long w = w0 + threadIdx.x; w < w1; w += kBlock) P.bm[P.W + w] = s_next[w - w0];   // F_1
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // layer 0's control state and decision (Algorithm 3 starts top-down)
+        LayerState S;
+        S.d = 0;
+        S.dir_prev = DIR_TD;
+        S.m_u = P.nnz;
+        S.v_u = P.n;
+        S.reached = 0;
+        S.reached_deg = 0;
+        S.pad[0] = S.pad[1] = S.pad[2] = 0;
+        const long long m_u = S.m_u - deg_r, v_u = S.v_u - 1;
+        const int cur = decide(P, S.dir_prev, 1, deg_r, m_u, v_u);
+        if (P.trace_cap > 0) {
+            LayerRec r;
+            r.dir = cur;
+            r.pad = 0;
+            r.n_f = 1;
+            r.m_f = deg_r;
+            r.m_u = m_u;
+            r.v_u = v_u;
+            P.trace[0] = r;
+        }
+        LayerState Nx = S;
+        Nx.d = 1;
+        Nx.dir_prev = cur;
+        Nx.m_u = m_u;
+        Nx.v_u = v_u;
+        Nx.reached = 1;
+        Nx.reached_deg = deg_r;
+        C->level = P.level;
+        C->parent = P.parent;
+        C->root = root;
+        C->done = 0;
+        C->nlayers = 0;
+        C->reached = 0;
+        C->reached_deg = 0;
+        C->status = 0;
+        C->bin_layer = -1;
+        C->st[0] = S;
+        C->st[1] = Nx;
+        C->parity = 1;
+    }
+    flush_counters(nf, mf, nh, &C->slot[1], s_red, kWavesPerBlock);
+}
+
 __global__ void __launch_bounds__(kFinishBlock) bfs_root_kernel(Params P)
 {
     __shared__ unsigned long long s_red[3 * (kFinishBlock / 64)];
@@ -988,6 +1110,12 @@ hipError_t launch_bin_scatter(const Params &p, int layer, int grid, hipStream_t 
 hipError_t launch_bin_reduce(const Params &p, int layer, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(bfs_bin_reduce_kernel, dim3(grid), dim3(kReduceBlock), 0, s, p, layer);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_root(const Params &p, int grid, int per, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_init_root_kernel, dim3(grid), dim3(kBlock), 0, s, p, per);
     return hipGetLastError();
 }
 

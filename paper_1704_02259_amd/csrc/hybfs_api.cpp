@@ -255,12 +255,19 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
             w->layer_ev.push_back(ev);
         }
     }
-    if ((e = launch_init(P, grid, s)) != hipSuccess) return hip_fail(e, "init launch");
+    // layer 0 is the root's own row: for a root of small degree it runs in the
+    // initialisation kernel (each block takes the neighbours in its own range)
+    // or, where that cannot be used, in one block instead of the grid
+    const bool small_root = g->h_deg[root] <= kRootKernelDegree;
+    const long long per = (g->W + grid - 1) / grid;
+    const bool fused = small_root && per <= kFuseWords && w->counters_zero;
+    w->counters_zero = false;
+    if ((e = fused ? launch_init_root(P, grid, (int)per, s) : launch_init(P, grid, s)) != hipSuccess)
+        return hip_fail(e, "init launch");
     for (int i = 0; i < L; ++i) {
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i], s)) != hipSuccess) return hip_fail(e, "event");
-        if (i == 0 && g->h_deg[root] <= kRootKernelDegree) {
-            // layer 0 is the root's own row: one block instead of the grid
-            if ((e = launch_root(P, s)) != hipSuccess) return hip_fail(e, "root launch");
+        if (i == 0 && small_root) {
+            if (!fused && (e = launch_root(P, s)) != hipSuccess) return hip_fail(e, "root launch");
             if (profile && (e = hipEventRecord(w->layer_ev[1], s)) != hipSuccess) return hip_fail(e, "event");
             continue;
         }
@@ -275,6 +282,7 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i + 1], s)) != hipSuccess) return hip_fail(e, "event");
     }
     if ((e = launch_finish(P, s)) != hipSuccess) return hip_fail(e, "finisher launch");
+    w->counters_zero = true;
     if (layers_enqueued) *layers_enqueued = L;
     return BFS_OK;
 }
@@ -350,7 +358,9 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     kp.kernelParams = init_args;
     if ((e = hipGraphExecKernelNodeSetParams(R.exec, R.init, &kp)) != hipSuccess)
         return hip_fail(e, "graph update");
+    w->counters_zero = false;
     if ((e = hipGraphLaunch(R.exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    w->counters_zero = true;   // the replayed finisher clears them
     if (layers_enqueued) *layers_enqueued = L;
     return BFS_OK;
 }

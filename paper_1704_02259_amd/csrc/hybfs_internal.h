@@ -36,6 +36,10 @@ struct Workspace {
     LayerRec *h_trace = nullptr;  // pinned
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> layer_ev;   // profile_layers: start/end per layer kernel
+    // every counter slot of `ctrl` is zero when the stream reaches the next
+    // traversal (the workspace was just cleared, or the last traversal was
+    // enqueued in full: its finisher clears them)
+    bool counters_zero = true;
     // binned top-down buckets (allocated on first use)
     void *bin_buf = nullptr;
     int *bin_cnt = nullptr, *bin_off = nullptr, *bin_cur = nullptr;

@@ -366,17 +366,36 @@ def test_first_writer_parents(torch, kron16, hyb, rule):
 
 
 def test_root_degree_paths(torch, kron16, hyb):
-    """Layer 0 runs in one block for roots of degree <= 4096 and in the grid
-    kernel above that: the highest-degree vertex, a degree-4096-ish vertex and
-    a leaf all give the oracle's output and per-layer counters."""
+    """Layer 0 runs inside the initialisation kernel for roots of degree <=
+    4096 and in the grid kernel above that: the highest-degree vertex, a
+    degree-4096-ish vertex and a leaf, in an order that alternates the two
+    paths on one workspace, all give the oracle's output and per-layer
+    counters."""
     g, G, _ = kron16
     deg = np.diff(g.off)
     order = np.argsort(deg)
     picks = [int(order[-1]), int(order[np.searchsorted(deg[order], 4096, side="right") - 1]),
-             int(order[np.searchsorted(deg[order], 1)])]
+             int(order[np.searchsorted(deg[order], 1)]), int(order[-1])]
     for r in picks:
         _say("root degree", int(deg[r]))
         lv, pa, st = _gpu_bfs(torch, G, r)
         _check_against_oracle(g, r, lv, pa, st)
         lv, pa, st = _gpu_bfs(torch, G, r, rule="bu")
         _check_against_oracle(g, r, lv, pa, st, "bu")
+
+
+def test_root_kernel_when_ranges_exceed_lds(torch, hyb):
+    """With a one-block grid on a graph of more than 2^16 vertices a block's
+    share of the bitmap exceeds what the fused initialisation kernel stages in
+    LDS, so layer 0 runs in its own one-block kernel; the default grid fuses
+    it.  Both give the oracle's output, also back to back on one stream."""
+    g = inputs.kronecker(17)
+    G = hyb.Graph.from_csr(g)
+    d = np.diff(g.off)
+    roots = [int(v) for v in np.nonzero((d > 0) & (d <= 4096))[0][:3]]
+    for grid in (1, 0, 1):
+        for r in roots:
+            _say("kron17 root", r, "grid", grid)
+            lv, pa, st = _gpu_bfs(torch, G, r, grid_blocks=grid)
+            _check_against_oracle(g, r, lv, pa, st)
+    G.close()
