@@ -346,6 +346,9 @@ def main():
     ap.add_argument("--alpha", type=int, default=0)
     ap.add_argument("--beta", type=int, default=0)
     ap.add_argument("--probe-k", type=int, default=-1)
+    ap.add_argument("--words-per-wave", type=int, default=0,
+                    help="bottom-up wavefront task size (0: library default); with any option given, "
+                         "no tuning pass runs")
     ap.add_argument("--first-writer", action="store_true",
                     help="first-writer top-down parents instead of canonical ones (validated, not compared)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-root leg (SCALE 22)")
@@ -412,6 +415,8 @@ def main():
         kw["probe_k"] = args.probe_k
     if args.first_writer:
         kw["first_writer"] = 1
+    if args.words_per_wave:
+        kw["words_per_wave"] = args.words_per_wave
 
     stream = torch.cuda.Stream()
     sp = stream.cuda_stream
@@ -523,7 +528,14 @@ def main():
         with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
             outs = list(ex.map(work, list(enumerate(int(r) for r in roots))))
         te = np.array([o[0] for o in outs])
-        balg_layers = [sum(min(td, bu) for td, bu in o[1]["per_layer"]) for o in outs[:nb]]
+        # the layers the layer kernel ran: from layer 0 or 1 (layer 0 of a
+        # root of small degree runs in the initialisation or a one-block
+        # kernel), one per launch; later layers belong to the finisher
+        balg_layers = []
+        for o, st in zip(outs[:nb], prof[:nb]):
+            first = 1 if st["layer0_kernel"] else 0
+            pl = o[1]["per_layer"][first:first + st["layer_launches"]]
+            balg_layers.append(sum(min(td, bu) for td, bu in pl))
         balg_total = [o[1]["bytes"] for o in outs[:nb]]
 
     gteps = te / (per_root_ms * 1e-3) / 1e9
@@ -545,7 +557,7 @@ def main():
         traffic = measured_traffic(args.workload)
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                    "kernel": "bfs_layer_kernel (layer 0: bfs_root_kernel)", "launches": launches_b,
+                    "kernel": "bfs_layer_kernel", "launches": launches_b,
                     "alg_bytes_per_launch": round(bytes_per_launch, 1), "avg_launch_us": round(avg_us, 3),
                     "traversal_frac": round(sum(balg_total) / (traversal_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}
 

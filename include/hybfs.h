@@ -196,13 +196,15 @@ typedef struct bfs_stats {
     int64_t reached_degree_sum; /* out: stored entries of reached vertices;
                                    half of it is the TEPS numerator (Section 6.3) */
     double  device_us;       /* out: HIP-event time of the whole traversal */
-    int32_t layer_launches;  /* out: layer kernels enqueued (some may find the
-                                traversal already finished); layer 0 of a
-                                root of degree <= 4096 is a one-block kernel
-                                and counts as one of them */
-    int32_t reserved;
-    double  layer_kernel_us; /* out: sum of the HIP-event durations of all layer
-                                kernels (profile_layers), else 0 */
+    int32_t layer_launches;  /* out: launches of the layer kernel (some may
+                                find the traversal already finished); layer 0
+                                is not among them when layer0_kernel != 0 */
+    int32_t layer0_kernel;   /* out: where layer 0 ran: 0 the layer kernel,
+                                1 a one-block kernel, 2 the initialisation
+                                kernel (roots of degree <= 4096); batched
+                                runs report 0 */
+    double  layer_kernel_us; /* out: sum of the HIP-event durations of those
+                                layer-kernel launches (profile_layers), else 0 */
 } bfs_stats;
 
 /*

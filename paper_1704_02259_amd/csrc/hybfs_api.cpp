@@ -231,7 +231,7 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
 }
 
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
-                      hipStream_t s, int *layers_enqueued, bool profile)
+                      hipStream_t s, int *layers_enqueued, bool profile, int *layer0_kernel)
 {
     // binned top-down: allowed on the layers after which its kernels are enqueued
     const bool bins = g->nbins <= kMaxBins && (opt.td_binned > 0 || (opt.td_binned == 0 && g->bin_auto));
@@ -283,7 +283,9 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     }
     if ((e = launch_finish(P, s)) != hipSuccess) return hip_fail(e, "finisher launch");
     w->counters_zero = true;
-    if (layers_enqueued) *layers_enqueued = L;
+    // launches of the layer kernel itself
+    if (layers_enqueued) *layers_enqueued = small_root ? L - 1 : L;
+    if (layer0_kernel) *layer0_kernel = fused ? 2 : small_root ? 1 : 0;
     return BFS_OK;
 }
 
@@ -657,12 +659,12 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
     }
 
     const bool profile = opt.profile_layers && stats && !opt.async;
-    int launched = 0;
+    int launched = 0, layer0 = 0;
     // the traversal's own events only serve stats->device_us: every event
     // record is a marker packet with its own cost on the device
     if (stats && (e = hipEventRecord(w->e0, s)) != hipSuccess) return hip_fail(e, "event record");
     if (!opt.graph_launch || profile)
-        rc = enqueue_traversal(g, w, opt, root, lvl, par, s, &launched, profile);
+        rc = enqueue_traversal(g, w, opt, root, lvl, par, s, &launched, profile, &layer0);
     else
         rc = enqueue_traversal_graph(g, w, opt, root, lvl, par, s, &launched);
     if (rc) return rc;
@@ -691,15 +693,19 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
         hipEventElapsedTime(&ms, w->e0, w->e1);
         stats->device_us = ms * 1000.0;
         stats->layer_launches = launched;
-        stats->reserved = 0;
+        stats->layer0_kernel = layer0;
         stats->layer_kernel_us = 0.0;
-        std::vector<double> kus(launched, 0.0);
+        // per enqueued layer: layer 0 first (its pair of events brackets the
+        // one-block kernel, or nothing when it ran in the initialisation
+        // kernel), then one layer-kernel launch each
+        const int nev = launched + (layer0 ? 1 : 0);
+        std::vector<double> kus(nev, 0.0);
         if (profile) {
-            for (int i = 0; i < launched; ++i) {
+            for (int i = 0; i < nev; ++i) {
                 float lm = 0.f;
                 hipEventElapsedTime(&lm, w->layer_ev[2 * i], w->layer_ev[2 * i + 1]);
                 kus[i] = lm * 1000.0;
-                stats->layer_kernel_us += kus[i];
+                if (i > 0 || !layer0) stats->layer_kernel_us += kus[i];
             }
         }
         const int nrec = std::min(c.nlayers, kTraceCap);
@@ -716,7 +722,7 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
                 o.m_f = r.m_f;
                 o.m_u = r.m_u;
                 o.v_u = r.v_u;
-                o.kernel_us = (profile && i < launched) ? kus[i] : 0.0;
+                o.kernel_us = (profile && i < nev) ? kus[i] : 0.0;
                 o.t_us = o.kernel_us;
             }
         }

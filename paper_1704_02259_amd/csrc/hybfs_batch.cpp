@@ -188,7 +188,7 @@ int bfs_run_batch(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t *leve
         stats->reached_degree_sum = 0;
         stats->device_us = 0.0;
         stats->layer_launches = 0;
-        stats->reserved = 0;
+        stats->layer0_kernel = 0;
         stats->layer_kernel_us = 0.0;
     }
     for (int g0 = 0; g0 < k; g0 += kLanes) {

@@ -132,6 +132,6 @@ int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int
                   const LanePtrs &out, hipStream_t s, bool profile, int *layers_enqueued);
 void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P);
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
-                      hipStream_t s, int *layers_enqueued, bool profile);
+                      hipStream_t s, int *layers_enqueued, bool profile, int *layer0_kernel = nullptr);
 
 }  // namespace hybfs

@@ -53,7 +53,7 @@ class bfs_stats(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int32), ("num_layers", ctypes.c_int32),
                 ("layers", ctypes.POINTER(bfs_layer_stat)), ("reached", ctypes.c_int64),
                 ("reached_degree_sum", ctypes.c_int64), ("device_us", ctypes.c_double),
-                ("layer_launches", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("layer_launches", ctypes.c_int32), ("layer0_kernel", ctypes.c_int32),
                 ("layer_kernel_us", ctypes.c_double)]
 
 
@@ -267,6 +267,7 @@ class Graph:
             return level, parent, {"num_layers": st.num_layers, "reached": st.reached,
                                    "reached_degree_sum": st.reached_degree_sum,
                                    "device_us": st.device_us, "layer_launches": st.layer_launches,
+                                   "layer0_kernel": st.layer0_kernel,
                                    "layer_kernel_us": st.layer_kernel_us,
                                    "layers": stats_layers(st, arr)}
         return level, parent
@@ -310,6 +311,7 @@ class Graph:
             return level, parent, {"num_layers": st.num_layers, "reached": st.reached,
                                    "reached_degree_sum": st.reached_degree_sum,
                                    "device_us": st.device_us, "layer_launches": st.layer_launches,
+                                   "layer0_kernel": st.layer0_kernel,
                                    "layer_kernel_us": st.layer_kernel_us,
                                    "layers": stats_layers(st, arr)}
         return level, parent

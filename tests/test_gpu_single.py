@@ -380,6 +380,7 @@ def test_root_degree_paths(torch, kron16, hyb):
         _say("root degree", int(deg[r]))
         lv, pa, st = _gpu_bfs(torch, G, r)
         _check_against_oracle(g, r, lv, pa, st)
+        assert st["layer0_kernel"] == (2 if deg[r] <= 4096 else 0)
         lv, pa, st = _gpu_bfs(torch, G, r, rule="bu")
         _check_against_oracle(g, r, lv, pa, st, "bu")
 
@@ -398,4 +399,5 @@ def test_root_kernel_when_ranges_exceed_lds(torch, hyb):
             _say("kron17 root", r, "grid", grid)
             lv, pa, st = _gpu_bfs(torch, G, r, grid_blocks=grid)
             _check_against_oracle(g, r, lv, pa, st)
+            assert st["layer0_kernel"] == (1 if grid == 1 else 2)
     G.close()
