@@ -76,8 +76,9 @@ typedef struct bfs_graph *bfs_graph_t;
 int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets,
                      const int32_t *col_indices, uint32_t flags, bfs_graph_t *out);
 
-/* Free the device copy and all workspaces.  The caller must ensure no
- * traversal on this graph is still running. */
+/* Free the device copy and all workspaces (waits for the device first).  The
+ * caller must not use the handle afterwards, nor destroy a graph that a
+ * server still holds.  Errors: BFS_E_INVALID (NULL handle). */
 int bfs_graph_destroy(bfs_graph_t g);
 
 typedef struct bfs_graph_info {
@@ -101,6 +102,8 @@ typedef struct bfs_graph_info {
                                       staging */
 } bfs_graph_info;
 
+/* Sizes and layout parameters of a resident graph, written to the caller's
+ * *info.  Errors: BFS_E_INVALID (NULL argument). */
 int bfs_graph_info_get(bfs_graph_t g, bfs_graph_info *info);
 
 /* ---- direction rules (Algorithm 3, switch functions f and g) ----
@@ -284,6 +287,9 @@ int bfs_autotune(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t mode, i
 
 /* ---- serving (continuous batching over resident graphs) ----
  *
+ * Not part of the paper: a request layer over bfs_run and bfs_run_batch,
+ * which implement its Algorithms 1-3.
+ *
  * A server holds graphs that are already resident (bfs_graph_create) and
  * answers single-root BFS queries on them.  `streams` worker slots, each
  * with its own HIP stream and host thread, run traversals concurrently, so
@@ -351,7 +357,8 @@ typedef struct bfs_serve_report {
 int bfs_serve_create(const bfs_serve_config *cfg, bfs_server_t *out);
 
 /* Register a resident graph; *graph_id receives its id (0, 1, ...).  The
- * caller keeps ownership and must not destroy the graph before the server. */
+ * caller keeps ownership and must not destroy the graph before the server.
+ * Errors: BFS_E_INVALID (NULL argument). */
 int bfs_serve_add_graph(bfs_server_t s, bfs_graph_t g, int32_t *graph_id);
 
 /* Queue one BFS query.  level_out / parent_out: int32[n] each, caller-owned,
@@ -371,18 +378,21 @@ int bfs_serve_poll(bfs_server_t s, uint64_t ticket, int32_t *done);
  * ticket and return the query's status; BFS_E_TIMEOUT leaves it pending. */
 int bfs_serve_wait(bfs_server_t s, uint64_t ticket, int64_t timeout_us);
 
-/* Counters and latency percentiles (see bfs_serve_report). */
+/* Counters and latency percentiles (see bfs_serve_report), written to the
+ * caller's *out.  Errors: BFS_E_INVALID (NULL argument). */
 int bfs_serve_stats(bfs_server_t s, bfs_serve_report *out);
 
-/* Zero the counters and latencies (e.g. after warm-up queries). */
+/* Zero the counters and latencies (e.g. after warm-up queries).
+ * Errors: BFS_E_INVALID (NULL server). */
 int bfs_serve_reset_stats(bfs_server_t s);
 
 /* Finish every queued and running query, then stop the workers and free the
- * server (graphs are not freed). */
+ * server (graphs are not freed).  Errors: BFS_E_INVALID (NULL server). */
 int bfs_serve_destroy(bfs_server_t s);
 
-/* Wait for all work enqueued on `stream` for this graph and report any
- * failure of asynchronous runs (BFS_E_DEVICE). */
+/* Wait for all work enqueued on `stream` (a HIP stream handle, NULL for the
+ * default stream) and report any failure of asynchronous runs.
+ * Errors: BFS_E_INVALID (NULL graph), BFS_E_DEVICE. */
 int bfs_graph_sync(bfs_graph_t g, void *stream);
 
 /* Message for the last failed call on this thread ("" if none). */
