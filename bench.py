@@ -86,7 +86,7 @@ class TimingEvent:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("bfs_kernels.hip", "bfs_device.h"):
+    for f in ("bfs_kernels.hip", "bfs_device.h", "bfs_wave.h"):
         with open(os.path.join(ROOT, "paper_1704_02259_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

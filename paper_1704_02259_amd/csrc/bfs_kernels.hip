@@ -900,6 +900,35 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
 // whole-grid launch would spend its time on launch and a bitmap scan.  The
 // direction Algorithm 3 picks for layer 0 is recorded as usual; a bottom-up
 // step from {root} would find exactly the same vertices and parents.
+// Layer 0's bookkeeping (F_0 = {root}, its degree deg_r): Algorithm 3's
+// decision for the root's row, the layer's trace entry, and the state that
+// layer 1 starts from.  S is the state before layer 0.
+__device__ void layer0_state(const Params &P, Ctrl *C, const LayerState &S, long long deg_r)
+{
+    const long long m_u = S.m_u - deg_r, v_u = S.v_u - 1;
+    const int cur = decide(P, S.dir_prev, 1, deg_r, m_u, v_u);
+    C->bin_layer = -1;
+    if (P.trace_cap > 0) {
+        LayerRec r;
+        r.dir = cur;
+        r.pad = 0;
+        r.n_f = 1;
+        r.m_f = deg_r;
+        r.m_u = m_u;
+        r.v_u = v_u;
+        P.trace[0] = r;
+    }
+    LayerState Nx = S;
+    Nx.d = 1;
+    Nx.dir_prev = cur;
+    Nx.m_u = m_u;
+    Nx.v_u = v_u;
+    Nx.reached = 1;
+    Nx.reached_deg = deg_r;
+    C->st[1] = Nx;
+    C->parity = 1;
+}
+
 // Per-BFS initialisation fused with layer 0, for a root of degree at most
 // kRootKernelDegree.  Block b owns bitmap words [b*per, (b+1)*per) and their
 // vertices: it writes their initial outputs and bitmap words, then takes the
@@ -981,25 +1010,6 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
         S.reached = 0;
         S.reached_deg = 0;
         S.pad[0] = S.pad[1] = S.pad[2] = 0;
-        const long long m_u = S.m_u - deg_r, v_u = S.v_u - 1;
-        const int cur = decide(P, S.dir_prev, 1, deg_r, m_u, v_u);
-        if (P.trace_cap > 0) {
-            LayerRec r;
-            r.dir = cur;
-            r.pad = 0;
-            r.n_f = 1;
-            r.m_f = deg_r;
-            r.m_u = m_u;
-            r.v_u = v_u;
-            P.trace[0] = r;
-        }
-        LayerState Nx = S;
-        Nx.d = 1;
-        Nx.dir_prev = cur;
-        Nx.m_u = m_u;
-        Nx.v_u = v_u;
-        Nx.reached = 1;
-        Nx.reached_deg = deg_r;
         C->level = P.level;
         C->parent = P.parent;
         C->root = root;
@@ -1008,10 +1018,8 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
         C->reached = 0;
         C->reached_deg = 0;
         C->status = 0;
-        C->bin_layer = -1;
         C->st[0] = S;
-        C->st[1] = Nx;
-        C->parity = 1;
+        layer0_state(P, C, S, deg_r);
     }
     flush_counters(nf, mf, nh, &C->slot[1], s_red, kWavesPerBlock);
 }
@@ -1024,29 +1032,7 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_root_kernel(Params P)
     const long long s0 = P.off[root], e0 = P.off[root + 1];
     const long long deg_r = e0 - s0;
     if (threadIdx.x == 0) {
-        const LayerState S = C->st[0];
-        const long long m_u = S.m_u - deg_r, v_u = S.v_u - 1;
-        const int cur = decide(P, S.dir_prev, 1, deg_r, m_u, v_u);
-        C->bin_layer = -1;
-        if (P.trace_cap > 0) {
-            LayerRec r;
-            r.dir = cur;
-            r.pad = 0;
-            r.n_f = 1;
-            r.m_f = deg_r;
-            r.m_u = m_u;
-            r.v_u = v_u;
-            P.trace[0] = r;
-        }
-        LayerState Nx = S;
-        Nx.d = 1;
-        Nx.dir_prev = cur;
-        Nx.m_u = m_u;
-        Nx.v_u = v_u;
-        Nx.reached = 1;
-        Nx.reached_deg = deg_r;
-        C->st[1] = Nx;
-        C->parity = 1;
+        layer0_state(P, C, C->st[0], deg_r);
         P.vis[root >> 6] |= 1ull << (root & 63);      // F_0 joins the finished layers
     }
     for (long long w = threadIdx.x; w < P.W; w += kFinishBlock) P.bm[2 * P.W + w] = 0ull;   // `next` of layer 1
