@@ -324,6 +324,32 @@ def test_async_runs_back_to_back(torch, kron16):
         assert np.array_equal(lv.cpu().numpy(), elv) and np.array_equal(pa.cpu().numpy(), epa)
 
 
+def test_mixed_launch_paths_on_one_stream(torch, kron16):
+    """One stream, one workspace: asynchronous runs that alternate the
+    captured graph (plain initialisation, grid-wide layer 0), the fused
+    initialisation with layer 0 (roots of degree <= 4096) and the grid-wide
+    layer 0 of a high-degree root.  The fused kernel relies on the counters
+    the previous traversal's finisher cleared, whichever path that traversal
+    took; every output equals the oracle's."""
+    g, G, roots = kron16
+    deg = np.diff(g.off)
+    hub = int(np.argmax(deg))
+    seq = [(int(roots[0]), 1), (int(roots[1]), 0), (hub, 0), (int(roots[2]), 0), (int(roots[3]), 1),
+           (int(roots[0]), 0), (hub, 1), (int(roots[1]), 0)]
+    s = torch.cuda.Stream()
+    outs = []
+    for r, graph in seq:
+        lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        pa = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        G.run(r, lv, pa, stream=s.cuda_stream, async_=1, graph_launch=graph)
+        outs.append((r, lv, pa))
+    from paper_1704_02259_amd import hybfs
+    hybfs.bfs_graph_sync(G.handle, s.cuda_stream)
+    for r, lv, pa in outs:
+        elv, epa = oracle.bfs(g, r)
+        assert np.array_equal(lv.cpu().numpy(), elv) and np.array_equal(pa.cpu().numpy(), epa), r
+
+
 def test_autotune_single_keeps_results(torch, kron16):
     """bfs_autotune (single-root mode) on other roots; the options it returns
     are valid and leave every root's output byte-identical to the oracle."""
