@@ -85,10 +85,17 @@ class TimingEvent:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the code the layer kernel is built from, with comments and
+    whitespace removed, so that only a change of code marks the committed
+    counter runs as stale."""
+    import re
     h = hashlib.sha256()
     for f in ("bfs_kernels.hip", "bfs_device.h", "bfs_wave.h"):
-        with open(os.path.join(ROOT, "paper_1704_02259_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1704_02259_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

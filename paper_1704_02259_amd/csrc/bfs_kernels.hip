@@ -4,8 +4,10 @@
 // direction decision, and runs either the top-down expansion (Algorithm 1) or
 // the bottom-up step (Algorithm 2 with the multiple-parents probes of
 // Algorithms 4-5).  Kernel boundaries order the layers; there is no grid-wide
-// barrier and no co-residency requirement.  A single-block finisher runs any
-// layers left after the enqueued layer kernels (very deep graphs).
+// barrier and no co-residency requirement.  For a root of small degree the
+// init kernel also runs layer 0 (each block takes the root's neighbours in
+// its own vertex range).  A single-block finisher runs any layers left after
+// the enqueued layer kernels (very deep graphs) and clears the counters.
 //
 // Device memory per traversal:
 //   vis      uint64 [W]  bit v&63 of word v>>6: v is in a finished layer, or has
