@@ -152,7 +152,9 @@ static long long footprint(const Graph *g, int k, bool host_out)
 
 void Server::worker(int i)
 {
-    hipSetDevice(dev);
+    // the server's device for this thread; should that fail, every query
+    // this slot takes fails with the error instead of running elsewhere
+    const hipError_t dev_err = hipSetDevice(dev);
     WorkerSlot &sl = slots[i];
     const bool host_out = !cfg.out_on_device;
     std::unique_lock<std::mutex> lk(mu);
@@ -220,6 +222,7 @@ void Server::worker(int i)
         }
         double te_group = 0.0;
         const Clock::time_point t_start = Clock::now();
+        if (rc == BFS_OK && dev_err != hipSuccess) rc = hip_fail(dev_err, "serving worker device");
         if (rc == BFS_OK) rc = run_group(i, g, rq, &te_group);
         const double run_us = std::chrono::duration<double, std::micro>(Clock::now() - t_start).count();
         const std::string err = rc != BFS_OK ? std::string(last_error()) : std::string();
