@@ -316,6 +316,38 @@ def sweep(torch, hybfs, dev, scales=(14, 16, 18, 20, 22), efs=(16, 32, 64), nroo
     return rows
 
 
+def host_output_leg(torch, hybfs, G, g, roots, kw, sp, te, dev_out):
+    """The same roots with the outputs in host memory: each synchronous run
+    includes the device-to-host copy of its 8n output bytes.  Host wall clock
+    per run, pageable numpy arrays and pinned tensors; never the headline."""
+    res = {"bytes_per_root": 8 * g.n}
+    for kind in ("pageable", "pinned"):
+        if kind == "pageable":
+            lv = np.empty(g.n, dtype=np.int32)
+            pa = np.empty(g.n, dtype=np.int32)
+            lp, pp = lv.ctypes.data, pa.ctypes.data
+        else:
+            lvt = torch.empty(g.n, dtype=torch.int32, pin_memory=True)
+            pat = torch.empty(g.n, dtype=torch.int32, pin_memory=True)
+            lp, pp = lvt.data_ptr(), pat.data_ptr()
+        opt = hybfs.bfs_options_init(out_on_device=0, stream=sp, **kw)
+        hybfs.bfs_run(G.handle, int(roots[0]), lp, pp, opt, None)
+        ts = []
+        for r in roots:
+            t0 = time.perf_counter()
+            hybfs.bfs_run(G.handle, int(r), lp, pp, opt, None)
+            ts.append(time.perf_counter() - t0)
+        ts = np.array(ts)
+        gt = te / ts / 1e9
+        # the last root's host outputs against its device run
+        hl, hp = (lv, pa) if kind == "pageable" else (lvt.numpy(), pat.numpy())
+        res[kind] = {"gteps_hm": round(float(len(gt) / np.sum(1.0 / gt)), 3),
+                     "median_root_us": round(float(np.median(ts)) * 1e6, 1),
+                     "copy_gbs_est": None,
+                     "equal_device_outputs": bool(np.array_equal(hl, dev_out[0]) and np.array_equal(hp, dev_out[1]))}
+    return res
+
+
 def layer_table(G, g, root, kw, torch, dev):
     """Per-layer breakdown of one traversal (the analogue of the paper's
     Tables 4-7): direction, frontier size and edges, HIP-event time of the
@@ -366,6 +398,8 @@ def main():
                     help="also print the per-layer breakdown of this many roots (stderr and JSON)")
     ap.add_argument("--tune-trials", type=int, default=48)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-host-out", action="store_true",
+                    help="skip the host-output leg (runs that include the device-to-host copy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -568,6 +602,18 @@ def main():
                     "alg_bytes_per_launch": round(bytes_per_launch, 1), "avg_launch_us": round(avg_us, 3),
                     "traversal_frac": round(sum(balg_total) / (traversal_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}
 
+    # host output buffers (device-to-host copy included), on the same roots
+    host_out = None
+    if not args.no_host_out:
+        G.run(int(roots[-1]), lv, pa, stream=sp, **kw)
+        stream.synchronize()
+        host_out = host_output_leg(torch, hybfs, G, g, roots, kw, sp, te, (lv.cpu().numpy(), pa.cpu().numpy()))
+        for kind in ("pageable", "pinned"):
+            # the copy's share of a run: against the device-output median of the timed loop
+            extra = host_out[kind]["median_root_us"] - float(np.median(per_root_ms)) * 1e3
+            host_out[kind]["copy_gbs_est"] = round(8 * g.n / (extra * 1e-6) / 1e9, 2) if extra > 0 else None
+        log("host outputs:", host_out)
+
     s = int(args.workload[4:]) if args.workload.startswith("kron") else None
     out = {
         "metric": METRIC,
@@ -593,6 +639,7 @@ def main():
         "min_root_gteps": round(float(gteps.min()), 3),
         "parity_sample_ok": parity_ok,
         "autotune": tuning,
+        "host_outputs": host_out,
     }
     if args.layer_table:
         out["layer_table"] = [layer_table(G, g, r, kw, torch, dev) for r in roots[:args.layer_table]]
