@@ -117,13 +117,20 @@ def test_repeat_runs_are_identical(torch, kron16):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_host_outputs_equal_device_outputs(torch, kron16):
+def test_host_outputs_equal_device_outputs(torch, hyb, kron16):
     g, G, roots = kron16
     r = int(roots[3])
-    lv, pa = G.run(r)              # numpy (host) outputs
+    lv, pa = G.run(r)              # numpy (host) outputs, pageable memory
     lv2, pa2, _ = _gpu_bfs(torch, G, r)
     assert np.array_equal(lv, lv2) and np.array_equal(pa, pa2)
     _check_against_oracle(g, r, lv, pa)
+    # pinned host buffers, filled with garbage first, on an explicit stream
+    lvp = torch.full((g.n,), 7, dtype=torch.int32, pin_memory=True)
+    pap = torch.full((g.n,), 7, dtype=torch.int32, pin_memory=True)
+    s = torch.cuda.Stream()
+    opt = hyb.hybfs.bfs_options_init(out_on_device=0, stream=s.cuda_stream)
+    hyb.hybfs.bfs_run(G.handle, r, lvp.data_ptr(), pap.data_ptr(), opt, None)
+    assert np.array_equal(lvp.numpy(), lv2) and np.array_equal(pap.numpy(), pa2)
 
 
 def _small_cases():
