@@ -552,7 +552,7 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     if (per_cu < 1 || cus < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
     g->cus = cus;
     g->blocks_per_cu = per_cu;
-    g->grid_default = std::min(per_cu, 4) * cus;
+    g->grid_default = std::min(per_cu, kLayerBlocksPerCu) * cus;
     // size a wavefront task so that about two tasks fall on each resident wave
     const long long resident_waves = (long long)g->grid_default * kWavesPerBlock;
     int wpg = 1;

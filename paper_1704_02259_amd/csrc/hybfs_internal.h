@@ -18,6 +18,11 @@ namespace hybfs {
 constexpr int kTraceCap = 4096;      // per-layer trace records kept on the device
 constexpr int kChunkLog2 = 8;        // top-down hub chunks cover 256 edges
 constexpr int kHubDegree = 256;      // above this degree, rows are split into hub-table chunks
+// Default layer-kernel blocks per CU (fewer where the occupancy query allows
+// fewer): five 256-thread blocks keep more dependent probe chains in flight
+// on the large bottom-up layers than four and cost nothing on small graphs;
+// a grid beyond one resident wave of blocks was slower.
+constexpr int kLayerBlocksPerCu = 5;
 // the batched bottom-up keeps a row position below hub_deg in one byte
 static_assert(kHubDegree <= 256, "batched pull stages row positions as bytes");
 
