@@ -104,11 +104,12 @@ struct Params {
     int nbins;
     int bin_log2;
     int serial_probes;                   // bottom-up: test frontier bits one at a time
-    int pad2;
+    int wide;                            // layers run in bfs_layer_kernel_wide
 };
 
 constexpr int kBinLog2 = 14;                   // destination tile: 16384 vertices, 64 KiB of minima in LDS
 constexpr int kMaxBins = 4096;
+constexpr int kWideWavesPerSimd = 6;           // residency the wide layer kernel is built for
 
 // ---------------------------------------------------------------------------
 // Batched multi-source traversal: lane b of every uint64 mask is root b.
@@ -210,8 +211,8 @@ constexpr int kFuseWords = 1024;
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);
 void *kernel_ptr_init();
-void *kernel_ptr_layer();
+void *kernel_ptr_layer(bool wide);
 void *kernel_ptr_finish();
-int layer_blocks_per_cu();
+int layer_blocks_per_cu(bool wide);
 
 }  // namespace hybfs

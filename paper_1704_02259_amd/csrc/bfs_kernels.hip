@@ -677,18 +677,39 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
     }
 }
 
-__global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, int allow_binned)
+// One layer over the whole grid; the body of both builds of the layer kernel.
+__device__ __forceinline__ void layer_grid(const Params &P, int layer, int allow_binned,
+                                           unsigned long long *s_red, LayerView *view, unsigned *hist)
 {
     const int parity = layer & 1;
-    __shared__ unsigned long long s_red[3 * kWavesPerBlock];
-    __shared__ LayerView view;
-    __shared__ unsigned hist[kMaxBins];
     const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
     run_layer(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
-              kWavesPerBlock, &view, false, layer, hist, allow_binned != 0 && P.nbins <= kMaxBins);
+              kWavesPerBlock, view, false, layer, hist, allow_binned != 0 && P.nbins <= kMaxBins);
+}
+
+__global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, int allow_binned)
+{
+    __shared__ unsigned long long s_red[3 * kWavesPerBlock];
+    __shared__ LayerView view;
+    __shared__ unsigned hist[kMaxBins];
+    layer_grid(P, layer, allow_binned, s_red, &view, hist);
+}
+
+// The same kernel built for kWideWavesPerSimd resident wavefronts per SIMD:
+// fewer registers (a few values spill), more wavefronts in flight.  On graphs
+// whose frontier bitmap no longer fits the L2, the layers are chains of
+// dependent probes and row loads, and more chains in flight win; on smaller
+// graphs the spills cost more than the extra wavefronts gain.
+__global__ void __launch_bounds__(kBlock, kWideWavesPerSimd) bfs_layer_kernel_wide(Params P, int layer,
+                                                                                  int allow_binned)
+{
+    __shared__ unsigned long long s_red[3 * kWavesPerBlock];
+    __shared__ LayerView view;
+    __shared__ unsigned hist[kMaxBins];
+    layer_grid(P, layer, allow_binned, s_red, &view, hist);
 }
 
 // One block runs whatever layers remain, with block barriers between them.
@@ -1079,7 +1100,10 @@ hipError_t launch_init(const Params &p, int grid, hipStream_t s)
 
 hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(bfs_layer_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    if (p.wide)
+        hipLaunchKernelGGL(bfs_layer_kernel_wide, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    else
+        hipLaunchKernelGGL(bfs_layer_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
     return hipGetLastError();
 }
 
@@ -1129,15 +1153,16 @@ hipError_t launch_iso_template(const long long *off, long long n, long long W,
 }
 
 void *kernel_ptr_init() { return (void *)bfs_init_kernel; }
-void *kernel_ptr_layer() { return (void *)bfs_layer_kernel; }
+void *kernel_ptr_layer(bool wide) { return wide ? (void *)bfs_layer_kernel_wide : (void *)bfs_layer_kernel; }
 void *kernel_ptr_finish() { return (void *)bfs_finish_kernel; }
 
-int layer_blocks_per_cu()
+int layer_blocks_per_cu(bool wide)
 {
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel, kBlock, 0) != hipSuccess)
-        return -1;
-    return occ;
+    const hipError_t e =
+        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel_wide, kBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel, kBlock, 0);
+    return e == hipSuccess ? occ : -1;
 }
 
 }  // namespace hybfs

@@ -220,6 +220,7 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->beta = opt.beta;
     P->first_writer = opt.first_writer;
     P->serial_probes = opt.bu_serial_probes > 0 || (opt.bu_serial_probes == 0 && g->n >= (1LL << 24));
+    P->wide = g->wide ? 1 : 0;
     P->nbins = g->nbins;
     P->bin_log2 = kBinLog2;
     P->bin_cnt = w->bin_cnt;
@@ -328,7 +329,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         int no_bins = 0;   // the captured sequence has no binned kernels
         for (int i = 0; i < L; ++i) {
             void *args[] = {&R.params, &layer_idx[i], &no_bins};
-            kp.func = kernel_ptr_layer();
+            kp.func = kernel_ptr_layer(R.params.wide != 0);
             kp.kernelParams = args;
             hipGraphNode_t node;
             if ((e = hipGraphAddKernelNode(&node, R.graph, &prev, 1, &kp)) != hipSuccess)
@@ -548,11 +549,12 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
 
     int cus = 0;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->dev);
-    const int per_cu = layer_blocks_per_cu();
+    g->wide = n >= kWideMinVertices;
+    const int per_cu = layer_blocks_per_cu(g->wide);
     if (per_cu < 1 || cus < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
     g->cus = cus;
     g->blocks_per_cu = per_cu;
-    g->grid_default = std::min(per_cu, kLayerBlocksPerCu) * cus;
+    g->grid_default = std::min(per_cu, g->wide ? kWideBlocksPerCu : kLayerBlocksPerCu) * cus;
     // size a wavefront task so that about two tasks fall on each resident wave
     const long long resident_waves = (long long)g->grid_default * kWavesPerBlock;
     int wpg = 1;

@@ -23,6 +23,10 @@ constexpr int kHubDegree = 256;      // above this degree, rows are split into h
 // on the large bottom-up layers than four and cost nothing on small graphs;
 // a grid beyond one resident wave of blocks was slower.
 constexpr int kLayerBlocksPerCu = 5;
+// From this many vertices the layers run in the wide build of the layer
+// kernel (six wavefronts per SIMD), six blocks per CU.
+constexpr long long kWideMinVertices = 1LL << 24;
+constexpr int kWideBlocksPerCu = 6;
 // the batched bottom-up keeps a row position below hub_deg in one byte
 static_assert(kHubDegree <= 256, "batched pull stages row positions as bytes");
 
@@ -110,6 +114,7 @@ struct Graph {
     std::vector<int32_t> h_deg;   // host copy of the degrees (launch choices)
     int cus = 0;
     int blocks_per_cu = 0;
+    bool wide = false;                   // layers in the wide build of the layer kernel
     int grid_default = 0;
     int wpg_default = 1;
     DepthTracker depth;                  // single-root traversals
