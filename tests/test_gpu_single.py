@@ -313,6 +313,25 @@ def test_graph_replay_alternating_roots_and_buffers(torch, kron16):
         _check_against_oracle(g, int(r), lv, pa, st)
 
 
+def test_wide_layer_kernel_direct_and_graph_replay(torch, hyb):
+    """From 2^24 vertices the layers run in the wide build of the layer kernel
+    (more wavefronts per SIMD, six blocks per CU).  A sparse 2^24-vertex graph
+    (Erdos-Renyi, mean degree 3, about 24 layers) traversed by direct launches
+    and by hipGraph replays, both byte for byte against the oracle."""
+    g = inputs.erdos_renyi(1 << 24, 3 << 23, seed=2424)
+    G = hyb.Graph.from_csr(g)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert G.info().grid_blocks > 5 * cus      # the wide launch shape was chosen
+    for r in inputs.pick_roots(g, 2, 77):
+        r = int(r)
+        _say("er2^24 root", r)
+        exp = oracle.bfs(g, r)
+        for graph in (0, 1, 1):
+            lv, pa, st = _gpu_bfs(torch, G, r, graph_launch=graph)
+            assert np.array_equal(lv, exp[0]) and np.array_equal(pa, exp[1]), (r, graph)
+    G.close()
+
+
 def test_async_runs_back_to_back(torch, kron16):
     """Asynchronous runs enqueued back to back on one stream, each into its own
     buffers, then one synchronisation."""
