@@ -84,12 +84,6 @@ class TimingEvent:
             pass
 
 
-def layer_kernel_name(n: int) -> str:
-    """The build of the layer kernel the library launches for a graph of n
-    vertices: the wide build (more wavefronts per SIMD) from 2^24 vertices."""
-    return "bfs_layer_kernel_wide" if n >= (1 << 24) else "bfs_layer_kernel"
-
-
 def kernel_source_hash() -> str:
     """Hash of the code the layer kernel is built from, with comments and
     whitespace removed, so that only a change of code marks the committed
@@ -604,7 +598,8 @@ def main():
         traffic = measured_traffic(args.workload)
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                    "kernel": layer_kernel_name(g.n), "launches": launches_b,
+                    "kernel": ("bfs_layer_kernel_wide" if G.info().layer_kernel_wide
+                               else "bfs_layer_kernel"), "launches": launches_b,
                     "alg_bytes_per_launch": round(bytes_per_launch, 1), "avg_launch_us": round(avg_us, 3),
                     "traversal_frac": round(sum(balg_total) / (traversal_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}
 

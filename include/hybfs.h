@@ -100,6 +100,11 @@ typedef struct bfs_graph_info {
     int64_t batch_workspace_bytes; /* device bytes of one batched workspace
                                       (bfs_run_batch), excluding host-output
                                       staging */
+    int32_t layer_kernel_wide; /* 1: the layers run in the build of the layer
+                                  kernel for more resident wavefronts
+                                  (bfs_layer_kernel_wide, graphs of 2^24
+                                  vertices and more), 0: bfs_layer_kernel */
+    int32_t reserved;
 } bfs_graph_info;
 
 /* Sizes and layout parameters of a resident graph, written to the caller's

@@ -617,6 +617,8 @@ int bfs_graph_info_get(bfs_graph_t gh, bfs_graph_info *info)
     info->hub_chunks = g->n_hub;
     info->typical_layers = g->depth.typical.load();
     info->batch_workspace_bytes = (int64_t)batch_workspace_bytes(g->n, g->W);
+    info->layer_kernel_wide = g->wide ? 1 : 0;
+    info->reserved = 0;
     return BFS_OK;
 }
 

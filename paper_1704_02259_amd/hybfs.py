@@ -64,7 +64,8 @@ class bfs_graph_info(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("slab_k", ctypes.c_int32),
                 ("chunk_edges", ctypes.c_int32), ("typical_layers", ctypes.c_int32),
                 ("hub_degree", ctypes.c_int32), ("hub_chunks", ctypes.c_int64),
-                ("batch_workspace_bytes", ctypes.c_int64)]
+                ("batch_workspace_bytes", ctypes.c_int64),
+                ("layer_kernel_wide", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class bfs_serve_config(ctypes.Structure):

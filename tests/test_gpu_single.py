@@ -322,6 +322,10 @@ def test_wide_layer_kernel_direct_and_graph_replay(torch, hyb):
     G = hyb.Graph.from_csr(g)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     assert G.info().grid_blocks > 5 * cus      # the wide launch shape was chosen
+    assert G.info().layer_kernel_wide == 1
+    small = hyb.Graph.from_csr(inputs.path_graph(100))
+    assert small.info().layer_kernel_wide == 0
+    small.close()
     for r in inputs.pick_roots(g, 2, 77):
         r = int(r)
         _say("er2^24 root", r)
