@@ -372,6 +372,291 @@ def layer_table(G, g, root, kw, torch, dev):
     return {"root": int(root), "layers": rows, "total_us": round(st["device_us"], 1)}
 
 
+def cpu_description() -> dict:
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cores": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def pinned_oracle_times(g, roots, budget_s: float):
+    """The serial oracle timed root by root on one core (the calling thread
+    pinned to the first core it may use, its previous affinity restored
+    afterwards), until budget_s seconds of CPU work are spent (at least one
+    root).  Returns the core, per-root seconds, TE and the oracle outputs."""
+    import oracle
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})
+    ts, tes, outs = [], [], {}
+    try:
+        for r in roots:
+            t0 = time.perf_counter()
+            elv, epa = oracle.bfs(g, int(r))
+            ts.append(time.perf_counter() - t0)
+            tes.append(oracle.traversed_edges(g, elv))
+            outs[int(r)] = (elv, epa)
+            if sum(ts) >= budget_s:
+                break
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    return core, ts, tes, outs
+
+
+def oracle_parity(torch, G, g, roots, kw, lv, pa, sp, stream, dev, have, nb):
+    """Every root's GPU level/parent (run with the timed options kw) against
+    oracle.bfs, compared on the device.  The oracle runs root by root in a
+    thread pool; `have` holds outputs already computed.  Also returns the
+    exact TE of every root and the algorithmic bytes of the first nb roots."""
+    import oracle
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def work(ir):
+        i, r = ir
+        if r in have:
+            elv, epa = have[r]
+        else:
+            elv, epa = oracle.bfs(g, r)
+        te_r = oracle.traversed_edges(g, elv)
+        ab = oracle.algorithmic_bytes(g, elv) if i < nb else None
+        return i, r, te_r, ab, elv, epa
+
+    te = np.zeros(len(roots))
+    abytes = [None] * len(roots)
+    bad = []
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        for i, r, te_r, ab, elv, epa in ex.map(work, [(i, int(r)) for i, r in enumerate(roots)]):
+            te[i] = te_r
+            abytes[i] = ab
+            G.run(r, lv, pa, stream=sp, **kw)
+            stream.synchronize()
+            ok = bool(torch.equal(lv, torch.from_numpy(elv).to(dev)) and
+                      torch.equal(pa, torch.from_numpy(epa).to(dev)))
+            if not ok:
+                bad.append(r)
+            if g.n >= (1 << 24) or i % 16 == 0:
+                log(f"oracle root {i} ({r}): TE {te_r:.0f}, equal {ok}")
+            del elv, epa
+    return te, abytes, bad, workers
+
+
+def single_root_leg(torch, hybfs, dev, workload, args, nroots, cpu_budget_s, balg_roots, host_outputs,
+                    layer_table_n=0, resident=None):
+    """Single-root hybrid BFS from nroots seeded roots of one graph: tuned
+    options, timed steps (HIP events per traversal), per-layer kernel times,
+    oracle parity of every root, roofline, CPU baseline.  Returns the result
+    dict and the generated graph."""
+    import inputs
+    t0 = time.time()
+    g = resident or inputs.workload_graph(workload)
+    roots = inputs.workload_roots(workload, g, nroots)
+    log(f"graph {workload}: n={g.n} nnz={g.nnz} gen {time.time() - t0:.1f}s, {len(roots)} roots")
+    t0 = time.time()
+    G = hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID)
+    info = G.info()
+    log(f"resident in {time.time() - t0:.1f}s; grid {info.grid_blocks}x{info.block_threads}, "
+        f"slab_k {info.slab_k}, hub degree {info.hub_degree}, hub chunks {info.hub_chunks}")
+
+    kw = {}
+    if args.alpha:
+        kw["alpha"] = args.alpha
+    if args.beta:
+        kw["beta"] = args.beta
+    if args.probe_k >= 0:
+        kw["probe_k"] = args.probe_k
+    if args.first_writer:
+        kw["first_writer"] = 1
+    if args.words_per_wave:
+        kw["words_per_wave"] = args.words_per_wave
+
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    tuning = None
+    if not args.no_autotune and not kw:
+        # tune on roots other than the measured ones (a different root seed)
+        s_ = int(workload[4:]) if workload.startswith("kron") else 20
+        troots = inputs.pick_roots(g, 16, inputs.ROOT_SEED.get(s_, 2020) + 500)
+        t0 = time.time()
+        topt, trep = G.autotune(troots, mode="single", max_trials=args.tune_trials, stream=sp)
+        kw = {k: v for k, v in topt.items() if k in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
+                                                       "words_per_wave", "bu_serial_probes")}
+        tuning = {"options": kw, "trials": trep["trials"], "tune_roots": len(troots),
+                  "speedup_on_tune_roots": round(trep["start_us"] / trep["best_us"], 3)}
+        log(f"autotune {time.time() - t0:.1f}s: {tuning}")
+    lv = torch.empty(g.n, dtype=torch.int32, device=dev)
+    pa = torch.empty(g.n, dtype=torch.int32, device=dev)
+
+    # one synchronous run per root first: adapts the launch depth, gives traces
+    traces = []
+    for r in roots:
+        _, _, st = G.run(int(r), lv, pa, stream=sp, stats=True, **kw)
+        traces.append(st)
+    log("layers per root:", sorted({st["num_layers"] for st in traces}))
+
+    def one_step(evs=None):
+        for i, r in enumerate(roots):
+            if evs is not None:
+                evs[i][0].record(stream)
+            G.run(int(r), lv, pa, stream=sp, async_=1, **kw)
+            if evs is not None:
+                evs[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    hybfs.bfs_graph_sync(G.handle, sp)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [[[TimingEvent(), TimingEvent()] for _ in roots] for _ in range(K)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(K):
+        one_step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    # the timed runs were asynchronous: any device-side failure raises here
+    hybfs.bfs_graph_sync(G.handle, sp)
+    per_root_ms = np.median(np.array([[a.elapsed_time(b) for a, b in evs[k]] for k in range(K)]), axis=0)
+    ms_per_step = wall * 1000.0 / K
+    default_ms = None
+    if tuning is not None:
+        # the same roots with the default options, for comparison
+        d_ev = [[TimingEvent(), TimingEvent()] for _ in roots]
+        for rep in range(2):
+            for i, r in enumerate(roots):
+                d_ev[i][0].record(stream)
+                G.run(int(r), lv, pa, stream=sp, async_=1)
+                d_ev[i][1].record(stream)
+            stream.synchronize()
+        hybfs.bfs_graph_sync(G.handle, sp)
+        default_ms = np.array([a.elapsed_time(b) for a, b in d_ev])
+    # per-query latency as a caller sees it: host wall clock of a synchronous
+    # run (device outputs, final stream synchronisation included), median of 3
+    sync_s = np.zeros((3, len(roots)))
+    for rep in range(3):
+        for i, r in enumerate(roots):
+            t0 = time.perf_counter()
+            G.run(int(r), lv, pa, stream=sp, **kw)
+            sync_s[rep, i] = time.perf_counter() - t0
+    sync_s = np.median(sync_s, axis=0)
+
+    # layer-kernel durations with HIP events around every launch (separate pass)
+    prof = []
+    for r in roots:
+        _, _, st = G.run(int(r), lv, pa, stream=sp, stats=True, profile_layers=1, **kw)
+        prof.append(st)
+
+    te = np.array([st["reached_degree_sum"] / 2.0 for st in traces])
+    cpu = parity_bad = balg_layers = balg_total = None
+    workers = None
+    if not args.no_cpu:
+        # serial oracle on one core, bounded sample of the same roots
+        core, cpu_t, cpu_te, have = pinned_oracle_times(g, roots, cpu_budget_s)
+        cpu_rates = np.array(cpu_te) / np.array(cpu_t) / 1e9
+        ci = cpu_description()
+        cpu = {"value": float(len(cpu_rates) / np.sum(1.0 / cpu_rates)), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle", "pinned_core": core, **ci,
+               "sample": f"first {len(cpu_t)} of the {len(roots)} roots, serial C oracle (FIFO BFS levels + "
+                         f"canonical-parent pass, gcc -O3), one thread pinned to core {core}; "
+                         f"{sum(cpu_t):.1f}s of CPU work"}
+        log(f"cpu oracle: {cpu['value']:.4f} GTEPS over {len(cpu_t)} roots on core {core} ({ci['cpu_model']})")
+        # every root against the oracle with the timed options; exact TE and
+        # algorithmic bytes from the oracle
+        nb = min(balg_roots, len(roots))
+        te, abytes, parity_bad, workers = oracle_parity(torch, G, g, [int(r) for r in roots], kw, lv, pa, sp,
+                                                        stream, dev, have, nb)
+        del have
+        log(f"parity of all {len(roots)} roots with the timed options: {'ok' if not parity_bad else parity_bad}")
+        # the layers the layer kernel ran: from layer 0 or 1 (layer 0 of a
+        # root of small degree runs in the initialisation or a one-block
+        # kernel), one per launch; later layers belong to the finisher
+        balg_layers = []
+        for ab, st in zip(abytes[:nb], prof[:nb]):
+            first = 1 if st["layer0_kernel"] else 0
+            pl = ab["per_layer"][first:first + st["layer_launches"]]
+            balg_layers.append(sum(min(td, bu) for td, bu in pl))
+        balg_total = [ab["bytes"] for ab in abytes[:nb]]
+
+    gteps = te / (per_root_ms * 1e-3) / 1e9
+    hm = float(len(gteps) / np.sum(1.0 / gteps))
+    if tuning is not None:
+        dg = te / (default_ms * 1e-3) / 1e9
+        tuning["value_default_options"] = round(float(len(dg) / np.sum(1.0 / dg)), 3)
+    agg = float(te.sum() / (ms_per_step * 1e-3) / 1e9)
+    sg = te / sync_s / 1e9
+
+    roofline = None
+    if balg_layers is not None:
+        nb = len(balg_layers)
+        launches_b = sum(prof[i]["layer_launches"] for i in range(nb))
+        us_b = sum(prof[i]["layer_kernel_us"] for i in range(nb))
+        bytes_per_launch = sum(balg_layers) / launches_b
+        avg_us = us_b / launches_b
+        achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
+        traversal_us = sum(per_root_ms[:nb]) * 1e3
+        traffic = measured_traffic(workload)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                    "kernel": ("bfs_layer_kernel_wide" if info.layer_kernel_wide else "bfs_layer_kernel"),
+                    "launches": launches_b, "roots_counted": nb,
+                    "alg_bytes_per_launch": round(bytes_per_launch, 1), "avg_launch_us": round(avg_us, 3),
+                    "traversal_frac": round(sum(balg_total) / (traversal_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}
+
+    host_out = None
+    if host_outputs:
+        # host output buffers (device-to-host copy included), on the same roots
+        G.run(int(roots[-1]), lv, pa, stream=sp, **kw)
+        stream.synchronize()
+        host_out = host_output_leg(torch, hybfs, G, g, roots, kw, sp, te, (lv.cpu().numpy(), pa.cpu().numpy()))
+        for kind in ("pageable", "pinned"):
+            # the copy's share of a run: against the device-output median of the timed loop
+            extra = host_out[kind]["median_root_us"] - float(np.median(per_root_ms)) * 1e3
+            host_out[kind]["copy_gbs_est"] = round(8 * g.n / (extra * 1e-6) / 1e9, 2) if extra > 0 else None
+        log("host outputs:", host_out)
+
+    s = int(workload[4:]) if workload.startswith("kron") else None
+    res = {
+        "value": round(hm, 3),
+        "ms_per_step": round(ms_per_step, 4),
+        "config": {"workload": (f"kronecker_scale{s}_ef16_{len(roots)}roots_single_root_hybrid_bfs"
+                                if s is not None else f"{workload}_{len(roots)}roots"),
+                   "n": g.n, "nnz": g.nnz, "roots": len(roots),
+                   "graph_seed": inputs.GRAPH_SEED.get(s) if s is not None else inputs.ER20_SEED},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "gteps_aggregate": round(agg, 3),
+        "median_root_us": round(float(np.median(per_root_ms)) * 1e3, 2),
+        "min_root_gteps": round(float(gteps.min()), 3),
+        "sync_wall": {"gteps_hm": round(float(len(sg) / np.sum(1.0 / sg)), 3),
+                      "median_root_us": round(float(np.median(sync_s)) * 1e6, 1),
+                      "p99_root_us": round(float(np.percentile(sync_s, 99)) * 1e6, 1)},
+        "parity_all_roots": None if parity_bad is None else not parity_bad,
+        "parity_options": kw,
+        "parity_oracle_threads": workers,
+        "autotune": tuning,
+        "host_outputs": host_out,
+    }
+    if parity_bad:
+        res["parity_failed_roots"] = parity_bad[:16]
+    if layer_table_n:
+        res["layer_table"] = [layer_table(G, g, r, kw, torch, dev) for r in roots[:layer_table_n]]
+        for t in res["layer_table"]:
+            log(f"layer table root {t['root']} ({t['total_us']} us):")
+            for row in t["layers"]:
+                log("  ", row)
+    G.close()
+    del lv, pa
+    torch.cuda.empty_cache()
+    return res, g
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,9 +664,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="kron20", help="kron<S> (edgefactor 16) or er20")
     ap.add_argument("--roots", type=int, default=64)
-    ap.add_argument("--cpu-sample", type=int, default=64, help="roots timed on the CPU oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU work spent timing the pinned serial oracle (at least one root)")
     ap.add_argument("--balg-roots", type=int, default=64, help="roots whose algorithmic bytes are counted")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
+    ap.add_argument("--no-s26", action="store_true", help="skip the SCALE-26 block")
+    ap.add_argument("--s26-balg-roots", type=int, default=4,
+                    help="SCALE-26 roots whose algorithmic bytes are counted (each takes ~30 s of CPU)")
     ap.add_argument("--alpha", type=int, default=0)
     ap.add_argument("--beta", type=int, default=0)
     ap.add_argument("--probe-k", type=int, default=-1)
@@ -436,218 +725,34 @@ def main():
                           "data": "synthetic"}), flush=True)
         return
 
-    t0 = time.time()
-    g = inputs.workload_graph(args.workload)
-    roots = inputs.workload_roots(args.workload, g, args.roots)
-    log(f"graph {args.workload}: n={g.n} nnz={g.nnz} gen {time.time() - t0:.1f}s, {len(roots)} roots")
-
-    t0 = time.time()
-    G = hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID)
-    info = G.info()
-    log(f"resident in {time.time() - t0:.1f}s; grid {info.grid_blocks}x{info.block_threads}, "
-        f"slab_k {info.slab_k}, hub degree {info.hub_degree}, hub chunks {info.hub_chunks}")
-
-    kw = {}
-    if args.alpha:
-        kw["alpha"] = args.alpha
-    if args.beta:
-        kw["beta"] = args.beta
-    if args.probe_k >= 0:
-        kw["probe_k"] = args.probe_k
-    if args.first_writer:
-        kw["first_writer"] = 1
-    if args.words_per_wave:
-        kw["words_per_wave"] = args.words_per_wave
-
-    stream = torch.cuda.Stream()
-    sp = stream.cuda_stream
-    tuning = None
-    if not args.no_autotune and not kw:
-        # tune on roots other than the measured ones (a different root seed)
-        s_ = int(args.workload[4:]) if args.workload.startswith("kron") else 20
-        troots = inputs.pick_roots(g, 16, inputs.ROOT_SEED.get(s_, 2020) + 500)
-        t0 = time.time()
-        topt, trep = G.autotune(troots, mode="single", max_trials=args.tune_trials, stream=sp)
-        kw = {k: v for k, v in topt.items() if k in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
-                                                       "words_per_wave", "bu_serial_probes")}
-        tuning = {"options": kw, "trials": trep["trials"], "tune_roots": len(troots),
-                  "speedup_on_tune_roots": round(trep["start_us"] / trep["best_us"], 3)}
-        log(f"autotune {time.time() - t0:.1f}s: {tuning}")
-    lv = torch.empty(g.n, dtype=torch.int32, device=dev)
-    pa = torch.empty(g.n, dtype=torch.int32, device=dev)
-
-    # one synchronous run per root first: adapts the launch depth, gives traces
-    traces = []
-    for r in roots:
-        _, _, st = G.run(int(r), lv, pa, stream=sp, stats=True, **kw)
-        traces.append(st)
-    log("layers per root:", sorted({st["num_layers"] for st in traces}))
-
-    def one_step(evs=None):
-        for i, r in enumerate(roots):
-            if evs is not None:
-                evs[i][0].record(stream)
-            G.run(int(r), lv, pa, stream=sp, async_=1, **kw)
-            if evs is not None:
-                evs[i][1].record(stream)
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-
-    K = args.steps
-    evs = [[[TimingEvent(), TimingEvent()]
-            for _ in roots] for _ in range(K)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(K):
-        one_step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    hybfs.bfs_graph_sync(G.handle, sp)
-    per_root_ms = np.median(np.array([[a.elapsed_time(b) for a, b in evs[k]] for k in range(K)]), axis=0)
-    default_ms = None
-    if tuning is not None:
-        # the same roots with the default options, for comparison
-        d_ev = [[TimingEvent(), TimingEvent()] for _ in roots]
-        for rep in range(2):
-            for i, r in enumerate(roots):
-                d_ev[i][0].record(stream)
-                G.run(int(r), lv, pa, stream=sp, async_=1)
-                d_ev[i][1].record(stream)
-            stream.synchronize()
-        default_ms = np.array([a.elapsed_time(b) for a, b in d_ev])
-    ms_per_step = wall * 1000.0 / K
-
-    # layer-kernel durations with HIP events around every launch (separate pass)
-    prof = []
-    for r in roots:
-        _, _, st = G.run(int(r), lv, pa, stream=sp, stats=True, profile_layers=1, **kw)
-        prof.append(st)
-    layer_launches = sum(st["layer_launches"] for st in prof)
-    layer_us = sum(st["layer_kernel_us"] for st in prof)
-
-    # ---- oracle legs (CPU) ----
-    import oracle
-    cpu = None
-    parity_ok = None
-    # without the oracle legs (profiling runs) the library's own count stands in
-    te = np.array([st["reached_degree_sum"] / 2.0 for st in traces])
-    balg_layers = None
-    if not args.no_cpu:
-        # serial oracle timed on a bounded sample of the same roots, 1 thread
-        ns = min(args.cpu_sample, len(roots))
-        cpu_t, cpu_te, levels = [], [], {}
-        parity_ok = True
-        for r in roots[:ns]:
-            t0 = time.perf_counter()
-            elv, epa = oracle.bfs(g, int(r))
-            cpu_t.append(time.perf_counter() - t0)
-            cpu_te.append(oracle.traversed_edges(g, elv))
-            G.run(int(r), lv, pa, stream=sp)
-            stream.synchronize()
-            parity_ok &= bool(np.array_equal(lv.cpu().numpy(), elv) and np.array_equal(pa.cpu().numpy(), epa))
-        cpu_rates = np.array(cpu_te) / np.array(cpu_t) / 1e9
-        cpu = {"value": float(len(cpu_rates) / np.sum(1.0 / cpu_rates)), "unit": "GTEPS", "cores": 1,
-               "kind": "oracle",
-               "sample": f"first {ns} of the {len(roots)} roots, serial C oracle (FIFO BFS levels + "
-                         f"canonical-parent pass, gcc -O2), one thread; {sum(cpu_t):.1f}s of CPU work"}
-        log(f"cpu oracle: {cpu['value']:.4f} GTEPS over {ns} roots; parity on sample: {parity_ok}")
-
-        # exact TE and algorithmic bytes per root from the oracle (not timed)
-        nb = min(args.balg_roots, len(roots))
-
-        def work(ir):
-            i, r = ir
-            elv, _ = oracle.bfs(g, int(r))
-            te_r = oracle.traversed_edges(g, elv)
-            res = oracle.algorithmic_bytes(g, elv) if i < nb else None
-            if g.n >= (1 << 24):
-                log(f"oracle root {i}: TE {te_r:.0f}")
-            return te_r, res
-
-        with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-            outs = list(ex.map(work, list(enumerate(int(r) for r in roots))))
-        te = np.array([o[0] for o in outs])
-        # the layers the layer kernel ran: from layer 0 or 1 (layer 0 of a
-        # root of small degree runs in the initialisation or a one-block
-        # kernel), one per launch; later layers belong to the finisher
-        balg_layers = []
-        for o, st in zip(outs[:nb], prof[:nb]):
-            first = 1 if st["layer0_kernel"] else 0
-            pl = o[1]["per_layer"][first:first + st["layer_launches"]]
-            balg_layers.append(sum(min(td, bu) for td, bu in pl))
-        balg_total = [o[1]["bytes"] for o in outs[:nb]]
-
-    gteps = te / (per_root_ms * 1e-3) / 1e9
-    hm = float(len(gteps) / np.sum(1.0 / gteps))
-    if tuning is not None:
-        dg = te / (default_ms * 1e-3) / 1e9
-        tuning["value_default_options"] = round(float(len(dg) / np.sum(1.0 / dg)), 3)
-    agg = float(te.sum() / (ms_per_step * 1e-3) / 1e9)
-
-    roofline = None
-    if balg_layers is not None:
-        nb = len(balg_layers)
-        launches_b = sum(prof[i]["layer_launches"] for i in range(nb))
-        us_b = sum(prof[i]["layer_kernel_us"] for i in range(nb))
-        bytes_per_launch = sum(balg_layers) / launches_b
-        avg_us = us_b / launches_b
-        achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
-        traversal_us = sum(per_root_ms[:nb]) * 1e3
-        traffic = measured_traffic(args.workload)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                    "kernel": ("bfs_layer_kernel_wide" if G.info().layer_kernel_wide
-                               else "bfs_layer_kernel"), "launches": launches_b,
-                    "alg_bytes_per_launch": round(bytes_per_launch, 1), "avg_launch_us": round(avg_us, 3),
-                    "traversal_frac": round(sum(balg_total) / (traversal_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}
-
-    # host output buffers (device-to-host copy included), on the same roots
-    host_out = None
-    if not args.no_host_out:
-        G.run(int(roots[-1]), lv, pa, stream=sp, **kw)
-        stream.synchronize()
-        host_out = host_output_leg(torch, hybfs, G, g, roots, kw, sp, te, (lv.cpu().numpy(), pa.cpu().numpy()))
-        for kind in ("pageable", "pinned"):
-            # the copy's share of a run: against the device-output median of the timed loop
-            extra = host_out[kind]["median_root_us"] - float(np.median(per_root_ms)) * 1e3
-            host_out[kind]["copy_gbs_est"] = round(8 * g.n / (extra * 1e-6) / 1e9, 2) if extra > 0 else None
-        log("host outputs:", host_out)
-
-    s = int(args.workload[4:]) if args.workload.startswith("kron") else None
+    main_leg, g = single_root_leg(torch, hybfs, dev, args.workload, args, args.roots, args.cpu_seconds,
+                                  args.balg_roots, not args.no_host_out, args.layer_table)
     out = {
         "metric": METRIC,
-        "value": round(hm, 3),
+        "value": main_leg.pop("value"),
         "unit": "GTEPS",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": main_leg.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": (f"kronecker_scale{s}_ef16_{len(roots)}roots_single_root_hybrid_bfs"
-                                if s is not None else f"{args.workload}_{len(roots)}roots"),
-                   "n": g.n, "nnz": g.nnz, "roots": len(roots),
-                   "graph_seed": inputs.GRAPH_SEED.get(s) if s is not None else inputs.ER20_SEED},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "gteps_aggregate": round(agg, 3),
-        "median_root_us": round(float(np.median(per_root_ms)) * 1e3, 2),
-        "min_root_gteps": round(float(gteps.min()), 3),
-        "parity_sample_ok": parity_ok,
-        "autotune": tuning,
-        "host_outputs": host_out,
+        "config": main_leg.pop("config"),
+        "roofline": main_leg.pop("roofline"),
+        "cpu_baseline": main_leg.pop("cpu_baseline"),
     }
-    if args.layer_table:
-        out["layer_table"] = [layer_table(G, g, r, kw, torch, dev) for r in roots[:args.layer_table]]
-        for t in out["layer_table"]:
-            log(f"layer table root {t['root']} ({t['total_us']} us):")
-            for row in t["layers"]:
-                log("  ", row)
+    out.update(main_leg)
+    if not args.no_s26 and args.workload == "kron20":
+        log("SCALE-26 block (64 roots) ...")
+        s26, g26 = single_root_leg(torch, hybfs, dev, "kron26", args, args.roots, args.cpu_seconds,
+                                   args.s26_balg_roots, False)
+        del g26
+        s26 = {"metric": METRIC, "unit": "GTEPS", **s26}
+        out["scale26"] = s26
+        log("scale26:", {k: s26[k] for k in ("value", "median_root_us", "parity_all_roots", "roofline")})
     if not args.no_batch and args.workload == "kron20":
         log("batched leg (SCALE 22, 64 roots) ...")
         out["batched"] = batched_leg(torch, hybfs, dev)

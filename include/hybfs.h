@@ -144,7 +144,9 @@ typedef struct bfs_options {
                                   finisher; 0 = adaptive per graph */
     int32_t out_on_device;     /* 1: level_out / parent_out are device pointers */
     int32_t async;             /* 1: return once enqueued (device outputs only, no
-                                  stats); errors surface in bfs_graph_sync */
+                                  stats); device-side failures are recorded and
+                                  reported by the next bfs_graph_sync of the graph
+                                  on the same stream */
     int32_t profile_layers;    /* 1: bracket every layer kernel with HIP events on
                                   the stream and report their durations in stats
                                   (synchronous runs with stats only) */
@@ -396,8 +398,15 @@ int bfs_serve_reset_stats(bfs_server_t s);
 int bfs_serve_destroy(bfs_server_t s);
 
 /* Wait for all work enqueued on `stream` (a HIP stream handle, NULL for the
- * default stream) and report any failure of asynchronous runs.
- * Errors: BFS_E_INVALID (NULL graph), BFS_E_DEVICE. */
+ * default stream) and report failures of the asynchronous runs of g on that
+ * stream (bfs_run and bfs_run_batch with opt->async = 1) since the previous
+ * bfs_graph_sync of g on that stream.  The finisher of every traversal
+ * records whether it ended normally and passed the device-side consistency
+ * checks; this call reads that record and clears it.  Outputs of a failed
+ * run are unspecified.
+ * Errors: BFS_E_INVALID (NULL graph), BFS_E_DEVICE (a HIP error, or at least
+ * one asynchronous run failed: the message counts them and names the status
+ * bits). */
 int bfs_graph_sync(bfs_graph_t g, void *stream);
 
 /* Message for the last failed call on this thread ("" if none). */

@@ -608,6 +608,8 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P, LaneP
         C->nlayers = 0;
         C->parity = 0;
         C->status = 0;
+        C->async_run = P.async_run;
+        C->fail_injected = P.fail_injected;
         C->pairs = 0;
         C->pairs_deg = 0;
         BLayerState S;
@@ -712,6 +714,8 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_batch_finish_kernel(BParams 
                           nullptr);
         __syncthreads();
     }
+    __syncthreads();
+    if (threadIdx.x == 0) record_failure(P.ctrl);
 }
 
 hipError_t launch_batch_init(const BParams &p, const LanePtrs &out, int grid, hipStream_t s)

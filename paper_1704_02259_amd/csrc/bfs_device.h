@@ -54,6 +54,13 @@ struct Ctrl {
     int *parent;
     int status;                      // nonzero: a device-side consistency check failed
     int bin_layer;                   // layer whose top-down step runs binned, else -1
+    int async_run;                   // the current traversal was enqueued asynchronously
+    int fail_injected;               // test hook: the finisher reports a failure (bit 0x200)
+    // failures of asynchronous traversals since the host last read them: the
+    // finisher of a failed async run adds one to err_runs and ORs its status
+    // (and 0x100 when it did not end normally) into err_bits
+    unsigned err_runs;
+    unsigned err_bits;
     LayerState st[2];
     Slot slot[kSlots];
 };
@@ -91,7 +98,7 @@ struct Params {
     int root;
     int rule;
     long long alpha, beta;
-    int pad1;
+    int async_run;                       // enqueued asynchronously (failures kept for bfs_graph_sync)
     int first_writer;                    // top-down parents by first writer, not minimum
     // binned top-down (large top-down layers): frontier edges are bucketed by
     // destination tile of 2^bin_log2 vertices, minima taken in LDS per tile
@@ -105,6 +112,7 @@ struct Params {
     int bin_log2;
     int serial_probes;                   // bottom-up: test frontier bits one at a time
     int wide;                            // layers run in bfs_layer_kernel_wide
+    int fail_injected;                   // test hook: report this traversal as failed
 };
 
 constexpr int kBinLog2 = 14;                   // destination tile: 16384 vertices, 64 KiB of minima in LDS
@@ -138,7 +146,10 @@ struct BCtrl {
     int nlayers;
     int parity;
     int status;
-    long long pad0[2];
+    int async_run;                   // as in Ctrl
+    int fail_injected;
+    unsigned err_runs;
+    unsigned err_bits;
     long long pairs;
     long long pairs_deg;
     long long pad[4];
@@ -179,8 +190,10 @@ struct BParams {
     int trace_cap;
     int wpg;                             // pull: bitmap words per wavefront task
     int wpg_td;                          // push: bitmap words per wavefront task
-    int pad;
+    int async_run;                       // enqueued asynchronously
     long long alpha, beta;
+    int fail_injected;                   // test hook: report this batch as failed
+    int pad;
 };
 
 // The init kernel copies `out` into the device tables p.lvl / p.par.

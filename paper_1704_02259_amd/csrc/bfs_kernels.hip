@@ -649,6 +649,8 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
     if (gt == 0) {
         Ctrl *C = P.ctrl;
         const long long deg_r = P.off[root + 1] - P.off[root];
+        C->async_run = P.async_run;
+        C->fail_injected = P.fail_injected;
         C->level = P.level;
         C->parent = P.parent;
         C->root = root;
@@ -735,6 +737,7 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
     unsigned long long *c = &P.ctrl->slot[0].c[0][0];
     constexpr int kCounters = (int)(sizeof(Slot) / sizeof(unsigned long long)) * kSlots;
     for (int i = threadIdx.x; i < kCounters; i += kFinishBlock) c[i] = 0ull;
+    if (threadIdx.x == 0) record_failure(P.ctrl);
 }
 
 // Bucket offsets of a binned layer (one block): exclusive scan of the
@@ -1041,6 +1044,8 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
         C->reached = 0;
         C->reached_deg = 0;
         C->status = 0;
+        C->async_run = P.async_run;
+        C->fail_injected = P.fail_injected;
         C->st[0] = S;
         layer0_state(P, C, S, deg_r);
     }

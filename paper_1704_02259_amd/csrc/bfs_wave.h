@@ -92,4 +92,24 @@ static __device__ __forceinline__ int lane_search(int key, int x)
     return lo;
 }
 
+// End of a traversal, in the finisher's thread 0: a traversal that did not
+// end normally or failed a device-side check is remembered for
+// bfs_graph_sync when it was enqueued asynchronously (a synchronous run reads
+// done and status itself).  Other kernels set status bits with device-scope
+// atomics, so the flags are read at that scope.
+template <class C_>
+__device__ void record_failure(C_ *C)
+{
+    const int dn = __hip_atomic_load(&C->done, __ATOMIC_RELAXED, AGENT);
+    unsigned st = __hip_atomic_load((unsigned *)&C->status, __ATOMIC_RELAXED, AGENT);
+    if (C->fail_injected) {
+        st |= 0x200u;
+        atomicOr((unsigned *)&C->status, 0x200u);
+    }
+    if (C->async_run && (dn != 1 || st != 0u)) {
+        C->err_runs += 1u;
+        C->err_bits |= st | (dn != 1 ? 0x100u : 0u);
+    }
+}
+
 }  // namespace hybfs

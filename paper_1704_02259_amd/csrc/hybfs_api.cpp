@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -166,6 +167,50 @@ int get_workspace(Graph *g, void *stream, Workspace **out)
     return BFS_OK;
 }
 
+// Reads (and clears) the failure record that the finishers of asynchronous
+// traversals keep in a workspace's control block.
+template <class W_, class C_>
+static int take_async_errors(W_ *w, C_ *h_ctrl, C_ *d_ctrl, hipStream_t s, unsigned *runs, unsigned *bits)
+{
+    std::lock_guard<std::mutex> wl(w->mu);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(&h_ctrl->err_runs, &d_ctrl->err_runs, 2 * sizeof(unsigned), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "reading the failure record");
+    if (h_ctrl->err_runs == 0) return BFS_OK;
+    *runs += h_ctrl->err_runs;
+    *bits |= h_ctrl->err_bits;
+    if ((e = hipMemsetAsync(&d_ctrl->err_runs, 0, 2 * sizeof(unsigned), s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "clearing the failure record");
+    return BFS_OK;
+}
+
+int check_async_errors(Graph *g, void *stream)
+{
+    Workspace *w = nullptr;
+    BatchWorkspace *bw = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        auto it = g->ws.find(stream);
+        if (it != g->ws.end()) w = it->second.get();
+        auto jt = g->bws.find(stream);
+        if (jt != g->bws.end()) bw = jt->second.get();
+    }
+    hipStream_t s = (hipStream_t)stream;
+    unsigned runs = 0, bits = 0;
+    int rc;
+    if (w && (rc = take_async_errors(w, w->h_ctrl, w->ctrl, s, &runs, &bits))) return rc;
+    if (bw && (rc = take_async_errors(bw, bw->h_ctrl, bw->ctrl, s, &runs, &bits))) return rc;
+    if (runs)
+        return set_error(BFS_E_DEVICE,
+                         "%u asynchronous traversal(s) on this stream failed a device-side check "
+                         "(status bits 0x%x; 0x100: did not end normally)",
+                         runs, bits);
+    return BFS_OK;
+}
+
 // Buckets of the binned top-down step, allocated with the first run that may
 // use them: counts, offsets and cursors per tile, and up to min(nnz, 2^28)
 // (parent, vertex) pairs.
@@ -214,11 +259,12 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->bm = w->bm;
     P->ctrl = w->ctrl;
     P->trace = w->trace;
-    P->trace_cap = kTraceCap;
+    P->trace_cap = w->trace ? kTraceCap : 0;   // no trace without a buffer for it
     P->rule = opt.rule;
     P->alpha = opt.alpha;
     P->beta = opt.beta;
     P->first_writer = opt.first_writer;
+    P->async_run = opt.async;
     P->serial_probes = opt.bu_serial_probes > 0 || (opt.bu_serial_probes == 0 && g->n >= (1LL << 24));
     P->wide = g->wide ? 1 : 0;
     P->nbins = g->nbins;
@@ -245,6 +291,7 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     P.root = root;
     P.level = lvl;
     P.parent = par;
+    P.fail_injected = root == g->fail_root;
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
     hipError_t e;
@@ -352,6 +399,8 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     R.params.root = root;
     R.params.level = lvl;
     R.params.parent = par;
+    R.params.async_run = opt.async;
+    R.params.fail_injected = root == g->fail_root;
     void *init_args[] = {&R.params};
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof kp);
@@ -569,6 +618,7 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     g->batch_grid = std::min(bper_cu, 4) * cus;
     g->nbins = (int)((n + (1LL << kBinLog2) - 1) >> kBinLog2);
     g->bin_auto = n >= (1LL << 23) && g->nbins <= kMaxBins;
+    if (const char *fr = getenv("HYBFS_TEST_FAIL_ROOT")) g->fail_root = atoi(fr);
     const int pper_cu = batch_pull_blocks_per_cu();
     if (pper_cu < 1) return set_error(BFS_E_DEVICE, "occupancy query failed");
     g->batch_pull_grid = pper_cu * cus;
@@ -739,7 +789,8 @@ int bfs_graph_sync(bfs_graph_t gh, void *stream)
     clear_error();
     if (!gh) return set_error(BFS_E_INVALID, "NULL graph");
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    return e == hipSuccess ? BFS_OK : hip_fail(e, "stream synchronize");
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    return check_async_errors(reinterpret_cast<Graph *>(gh), stream);
 }
 
 }  // extern "C"

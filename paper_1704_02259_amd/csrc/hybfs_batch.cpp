@@ -93,6 +93,7 @@ static void fill_batch_params(const Graph *g, const BatchWorkspace *w, const bfs
     P->wpg_td = 64;
     P->alpha = opt.alpha;
     P->beta = opt.beta;
+    P->async_run = opt.async;
 }
 
 // [init, seed, L x (push, pull), finisher] for one group of at most 64 roots.
@@ -102,7 +103,10 @@ int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int
     BParams P;
     fill_batch_params(g, w, opt, k, &P);
     RootSet R;
-    for (int i = 0; i < kLanes; ++i) R.r[i] = i < k ? roots[i] : -1;
+    for (int i = 0; i < kLanes; ++i) {
+        R.r[i] = i < k ? roots[i] : -1;
+        if (i < k && roots[i] == g->fail_root) P.fail_injected = 1;
+    }
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_grid;
     const int pgrid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_pull_grid;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->batch_depth.typical.load();

@@ -123,6 +123,8 @@ struct Graph {
     bool bin_auto = false;               // binned top-down on by default (large graphs)
     int batch_grid = 0;                  // blocks of the batched push kernel
     int batch_pull_grid = 0;             // blocks of the batched pull kernel (kPullWaves waves each)
+    int fail_root = -1;                  // test hook (HYBFS_TEST_FAIL_ROOT): traversals from this
+                                         // root report a device-side failure
     std::mutex mu;
     std::map<void *, std::unique_ptr<Workspace>> ws;
     std::map<void *, std::unique_ptr<BatchWorkspace>> bws;
@@ -136,6 +138,10 @@ int validate_options(const bfs_options &o);
 int check_csr(int64_t n, int64_t nnz, const int64_t *off, const int32_t *col, bool need_sorted,
               bool check_symmetry);
 int get_workspace(Graph *g, void *stream, Workspace **out);
+// Failures of asynchronous traversals of g on `stream` since the last call
+// (the stream must be synchronized): BFS_E_DEVICE with a message, and the
+// record cleared; BFS_OK when there were none.
+int check_async_errors(Graph *g, void *stream);
 size_t batch_workspace_bytes(long long n, long long W);
 int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out);
 int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,

@@ -65,6 +65,8 @@ struct Tuner {
             hipEventElapsedTime(&ms, e0, e1);
             best = std::min(best, (double)ms * 1000.0);
         }
+        // the timed passes ran asynchronously: their failures surface here
+        if ((rc = check_async_errors(g, (void *)s))) return rc;
         ++trials;
         *us = best;
         return BFS_OK;

@@ -214,6 +214,23 @@ def stats_layers(st: bfs_stats, arr) -> list[dict]:
     return out
 
 
+def _check_out_tensors(torch, level, parent, need: int):
+    """Output tensors must be contiguous int32 device tensors of at least
+    `need` elements each (checked here because the library only sees
+    pointers)."""
+    for name, t in (("level", level), ("parent", parent)):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor, got {type(t).__name__}")
+        if t.dtype != torch.int32:
+            raise TypeError(f"{name} must be int32, got {t.dtype}")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() < need:
+            raise ValueError(f"{name} has {t.numel()} elements, needs {need}")
+
+
 class Graph:
     """A graph resident on the current GPU (wraps bfs_graph_create)."""
 
@@ -253,9 +270,7 @@ class Graph:
             parent = np.empty(self.n, dtype=np.int32)
             lp, pp = level.ctypes.data, parent.ctypes.data
         else:
-            assert level.dtype == torch.int32 and parent.dtype == torch.int32
-            assert level.is_cuda and parent.is_cuda and level.is_contiguous() and parent.is_contiguous()
-            assert level.numel() >= self.n and parent.numel() >= self.n
+            _check_out_tensors(torch, level, parent, self.n)
             lp, pp = level.data_ptr(), parent.data_ptr()
             if stream is None:
                 stream = torch.cuda.current_stream().cuda_stream
@@ -297,9 +312,7 @@ class Graph:
             parent = np.empty((k, self.n), dtype=np.int32)
             lp, pp = level.ctypes.data, parent.ctypes.data
         else:
-            assert level.dtype == torch.int32 and parent.dtype == torch.int32
-            assert level.is_cuda and parent.is_cuda and level.is_contiguous() and parent.is_contiguous()
-            assert level.numel() >= k * self.n and parent.numel() >= k * self.n
+            _check_out_tensors(torch, level, parent, k * self.n)
             lp, pp = level.data_ptr(), parent.data_ptr()
             if stream is None:
                 stream = torch.cuda.current_stream().cuda_stream

@@ -132,3 +132,18 @@ def test_binding_raises_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(hybfs, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         hybfs.load()
+
+
+def test_binding_checks_output_tensors_before_the_call():
+    """Wrong dtype, host memory, non-contiguous or short outputs raise in the
+    binding (explicit checks, kept under python -O) before any pointer reaches
+    the library."""
+    import torch
+    from paper_1704_02259_amd import hybfs
+    good = torch.zeros(8, dtype=torch.int32)
+    with pytest.raises(TypeError):
+        hybfs._check_out_tensors(torch, np.zeros(8, np.int32), good, 8)
+    with pytest.raises(TypeError):
+        hybfs._check_out_tensors(torch, torch.zeros(8, dtype=torch.int64), good, 8)
+    with pytest.raises(ValueError, match="device"):
+        hybfs._check_out_tensors(torch, good, good, 8)
