@@ -409,6 +409,40 @@ int bfs_serve_destroy(bfs_server_t s);
  * bits). */
 int bfs_graph_sync(bfs_graph_t g, void *stream);
 
+/* ---- traversal without device allocation ----
+ *
+ * For callers that cannot allocate device memory: code that must not call
+ * hipMalloc (work recorded under stream capture, tight serving loops, hosts
+ * that forbid allocation after start-up).
+ *
+ * Same traversal and result as bfs_run (byte for byte), but its device scratch
+ * (visited bitmap, the three rotating frontier bitmaps, control block and
+ * layer trace) lives in one file-scope device array of the library instead
+ * of a per-stream workspace.  The array holds graphs of up to
+ * BFS_NOALLOC_MAX_VERTICES vertices (32.2 MiB); every device the library is
+ * loaded on holds its own copy until the process ends.  The call allocates
+ * no device or pinned memory: no hipMalloc, hipFree or allocating library
+ * routine.  Differences from bfs_run:
+ *   - outputs must be device pointers (opt->out_on_device = 1; with opt ==
+ *     NULL the defaults are taken with device outputs);
+ *   - synchronous only: opt->async, opt->profile_layers and opt->graph_launch
+ *     must be 0;
+ *   - the binned top-down step is not used (its buckets would need an
+ *     allocation; results do not depend on it);
+ *   - stats->device_us and the per-layer times are 0 (no events).
+ * The graph must live on the current device.  All calls on one device share
+ * its array, which keeps the last call's contents; the library runs them one
+ * at a time (a lock per device), so concurrent calls from several threads
+ * queue up rather than race.  The array is initialised on the first call on
+ * each device.
+ * Errors: BFS_E_INVALID (graph larger than BFS_NOALLOC_MAX_VERTICES, host or
+ * asynchronous outputs, graph on another device, bad root or options),
+ * BFS_E_DEVICE.
+ */
+#define BFS_NOALLOC_MAX_VERTICES (1LL << 26)
+int bfs_run_noalloc(bfs_graph_t g, int32_t root, int32_t *level_out, int32_t *parent_out,
+                    const bfs_options *opt, bfs_stats *stats);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *bfs_last_error(void);
 

@@ -122,6 +122,8 @@ def load():
         "bfs_run_batch": (ctypes.c_int, [vp, vp, i32, vp, vp, ctypes.POINTER(bfs_options),
                                          ctypes.POINTER(bfs_stats)]),
         "bfs_graph_sync": (ctypes.c_int, [vp, vp]),
+        "bfs_run_noalloc": (ctypes.c_int, [vp, i32, vp, vp, ctypes.POINTER(bfs_options),
+                                           ctypes.POINTER(bfs_stats)]),
         "bfs_autotune": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.POINTER(bfs_options),
                                         ctypes.POINTER(bfs_tune_report)]),
         "bfs_serve_config_init": (None, [ctypes.POINTER(bfs_serve_config)]),
@@ -184,6 +186,13 @@ def bfs_run(g: int, root: int, level_out: int, parent_out: int, opt: bfs_options
     _check(load().bfs_run(g, root, level_out, parent_out,
                           ctypes.byref(opt) if opt is not None else None,
                           ctypes.byref(stats) if stats is not None else None))
+
+
+def bfs_run_noalloc(g: int, root: int, level_out: int, parent_out: int, opt: bfs_options | None = None,
+                    stats: bfs_stats | None = None):
+    _check(load().bfs_run_noalloc(g, root, level_out, parent_out,
+                                  ctypes.byref(opt) if opt is not None else None,
+                                  ctypes.byref(stats) if stats is not None else None))
 
 
 def bfs_run_batch(g: int, roots: int, k: int, level_out: int, parent_out: int,
@@ -285,6 +294,25 @@ class Graph:
                                    "device_us": st.device_us, "layer_launches": st.layer_launches,
                                    "layer0_kernel": st.layer0_kernel,
                                    "layer_kernel_us": st.layer_kernel_us,
+                                   "layers": stats_layers(st, arr)}
+        return level, parent
+
+    def run_noalloc(self, root: int, level, parent, stream=None, stats: bool = False, **kw):
+        """bfs_run_noalloc: one BFS into device tensors, with the library's
+        fixed device scratch instead of a workspace allocation."""
+        import torch
+        _check_out_tensors(torch, level, parent, self.n)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        opt = bfs_options_init(out_on_device=1, stream=stream, **kw)
+        st = arr = None
+        if stats:
+            st, arr = make_stats(4096)
+        bfs_run_noalloc(self.handle, int(root), level.data_ptr(), parent.data_ptr(), opt, st)
+        if stats:
+            return level, parent, {"num_layers": st.num_layers, "reached": st.reached,
+                                   "reached_degree_sum": st.reached_degree_sum,
+                                   "layer_launches": st.layer_launches, "layer0_kernel": st.layer0_kernel,
                                    "layers": stats_layers(st, arr)}
         return level, parent
 

@@ -88,6 +88,12 @@ def test_run_rejects_null_graph(lib):
     assert rc == -1 and "graph" in lib.bfs_last_error().decode()
 
 
+def test_run_noalloc_rejects_null_graph(lib):
+    z = np.zeros(4, np.int32)
+    rc = lib.bfs_run_noalloc(None, 0, z.ctypes.data, z.ctypes.data, None, None)
+    assert rc == -1 and "graph" in lib.bfs_last_error().decode()
+
+
 def test_run_batch_rejects_null_graph(lib):
     z = np.zeros(4, np.int32)
     rc = lib.bfs_run_batch(None, z.ctypes.data, 1, z.ctypes.data, z.ctypes.data, None, None)
