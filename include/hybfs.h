@@ -175,8 +175,31 @@ typedef struct bfs_options {
                                   a time when the frontier bitmap is 2 MiB or more
                                   (n >= 2^24), where each probe costs a cache line
                                   of bandwidth */
-    int32_t reserved3;
+    int32_t td_queue;          /* frontier queues (Algorithm 1's output queue, with
+                                  the bitmap/queue conversions of Section 4): a
+                                  top-down layer whose frontier was also written as
+                                  a queue expands the queue instead of scanning the
+                                  frontier bitmap.  1 = top-down layers (and layer 0)
+                                  append what they discover to the next queue
+                                  (wavefront-aggregated appends) and a top-down layer
+                                  after one of them reads it; 2 = every layer writes
+                                  its output as a queue too (bottom-up and binned
+                                  steps convert their output bitmap words), so every
+                                  top-down layer reads one; -1 = bitmaps only;
+                                  0 (default) = the library's choice */
     void   *stream;            /* hipStream_t to run on; NULL = default stream */
+    int32_t td_hub_list;       /* hub lists: a step that discovers a vertex above
+                                  the top-down degree cut-off appends its edge
+                                  chunks to the next frontier's hub list, and a
+                                  top-down layer whose frontier has such a list
+                                  expands its hubs from it instead of scanning the
+                                  graph's whole table of hub chunks against the
+                                  frontier bitmap (a list longer than a quarter of
+                                  the table is abandoned for the table).  1 = every
+                                  step keeps them; 2 = only layer 0 (the root's
+                                  row), for layer 1; -1 = never; 0 (default) = the
+                                  library's choice */
+    int32_t reserved4;
 } bfs_options;
 
 /* Fill defaults: edge rule, alpha 14, beta 24, probe_k 8, td_hub_degree 256,

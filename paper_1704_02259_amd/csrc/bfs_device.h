@@ -20,8 +20,19 @@ enum { RULE_EDGES = 0, RULE_TABLE = 1, RULE_TOPDOWN = 2, RULE_BOTTOMUP = 3 };
 // atomics of a layer spread over kSub addresses; readers sum the sub-counters.
 constexpr int kSub = 16;
 struct Slot {
-    unsigned long long c[kSub][8];   // c[k][0]: part of |F_d|, c[k][1]: part of sum deg(F_d)
+    unsigned long long c[kSub][8];   // c[k][0]: part of |F_d|, c[k][1]: part of sum deg(F_d),
+                                     // c[k][2]: part of the count of F_d's vertices above
+                                     // hub_deg; c[0][3]: entries of F_d's hub list,
+                                     // c[0][4]: entries of F_d's queue (appended by atomics
+                                     // on these single addresses)
 };
+constexpr int kHubTail = 3;
+constexpr int kQueueTail = 4;
+
+// How the frontier F_d is available besides its bitmap (LayerState::qform).
+enum { QF_NONE = 0,                  // bitmap only
+       QF_LIST = 1,                  // queue of F_d; F_d is not yet in vis
+       QF_LIST_VIS = 2 };            // queue of F_d; F_d is already in vis
 
 // What the kernel of layer d needs from the layers before it.  Two copies
 // alternate: the kernel of layer d reads st[d & 1] and its block 0 writes
@@ -33,7 +44,9 @@ struct LayerState {
     long long v_u;                   // vertices not in layers 0..d-1
     long long reached;               // vertices in layers 0..d-1
     long long reached_deg;           // their degree sum
-    long long pad[3];
+    int qform;                       // QF_*: F_d's queue, written by the layer before
+    int hlist;                       // 1: F_d's hub list was written (complete unless too long)
+    long long pad[2];
 };
 
 // Trace of one processed layer, written by block 0.
@@ -54,6 +67,8 @@ struct Ctrl {
     int *parent;
     int status;                      // nonzero: a device-side consistency check failed
     int bin_layer;                   // layer whose top-down step runs binned, else -1
+    int bin_qlen;                    // that layer's frontier: queue length, or -1 for the bitmap
+    int bin_hlist;                   // that layer's hubs come from the hub list
     int async_run;                   // the current traversal was enqueued asynchronously
     int fail_injected;               // test hook: the finisher reports a failure (bit 0x200)
     // failures of asynchronous traversals since the host last read them: the
@@ -113,7 +128,41 @@ struct Params {
     int serial_probes;                   // bottom-up: test frontier bits one at a time
     int wide;                            // layers run in bfs_layer_kernel_wide
     int fail_injected;                   // test hook: report this traversal as failed
+    // frontier queues (Algorithm 1's output queue): q0 (even d) and q1 (odd
+    // d) hold F_d as a list of vertex ids, appended by the producers of F_d.
+    // Two named pointers, not an array: a runtime index into the parameter
+    // block would move the whole block into private memory.
+    int *q0, *q1;
+    long long q_cap;                     // entries of each (n)
+    int td_queue;                        // QM_*: which layers write and read queues
+    // hub lists: the 2^chunk_log2-edge chunks of F_d's vertices above hub_deg,
+    // appended by whichever step discovers them; a top-down layer expands its
+    // hubs from the list instead of scanning the graph's whole hub table
+    int hub_list;                        // HL_*: which steps write hub lists
+    Item *hq0, *hq1;                     // even and odd layers
+    long long hq_cap;                    // entries of each (the table's size bounds them)
+    int q_write;                         // set per layer: this layer appends its output to
+                                         // the next frontier's queue
+    int pad1;
 };
+
+__device__ __forceinline__ int *queue_of(const Params &P, int d) { return (d & 1) ? P.q1 : P.q0; }
+__device__ __forceinline__ Item *hubs_of(const Params &P, int d) { return (d & 1) ? P.hq1 : P.hq0; }
+
+// Hub-list modes (Params::hub_list).  A top-down layer reads its frontier's
+// hub list whenever the layer before wrote one.
+enum { HL_OFF = 0,
+       HL_ALL = 1,                       // every step lists the hubs it discovers
+       HL_LAYER0 = 2 };                  // only layer 0 (the root's row) does, for layer 1
+
+// Queue modes (Params::td_queue).
+enum { QM_OFF = 0,                       // bitmaps only
+       QM_TOPDOWN = 1,                   // top-down layers (and layer 0) write their output
+                                         // queue; a top-down layer reads its input queue
+                                         // when the layer before left one
+       QM_ALL = 2 };                     // every layer writes its output as a queue too
+                                         // (bottom-up and binned steps convert their output
+                                         // bitmap words), every top-down layer reads one
 
 constexpr int kBinLog2 = 14;                   // destination tile: 16384 vertices, 64 KiB of minima in LDS
 constexpr int kMaxBins = 4096;
@@ -210,6 +259,8 @@ constexpr int kPullWaves = 4;             // wavefronts per block of the batched
 hipError_t launch_init(const Params &p, int grid, hipStream_t s);
 // allow_binned: the three binned kernels follow this layer kernel in the stream
 hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s);
+// whether layer `layer` runs in the build of the layer kernel with queues and hub lists
+bool layer_uses_lists(const Params &p, int layer);
 hipError_t launch_bin_scan(const Params &p, int layer, hipStream_t s);
 hipError_t launch_bin_scatter(const Params &p, int layer, int grid, hipStream_t s);
 hipError_t launch_bin_reduce(const Params &p, int layer, int grid, hipStream_t s);
@@ -224,8 +275,8 @@ constexpr int kFuseWords = 1024;
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);
 void *kernel_ptr_init();
-void *kernel_ptr_layer(bool wide);
-void *kernel_ptr_finish();
+void *kernel_ptr_layer(bool wide, bool lists);   // lists: the build with queues and hub lists
+void *kernel_ptr_finish(bool lists);
 int layer_blocks_per_cu(bool wide);
 
 }  // namespace hybfs

@@ -49,6 +49,203 @@ __device__ __forceinline__ int decide(const Params &P, int cur, long long n_f, l
 }
 
 // ---------------------------------------------------------------------------
+// Lists of the next frontier F_{d+1}.  Every helper here runs with all lanes
+// of the wavefront active; a lane without an entry passes false.
+
+// Algorithm 1's out.add, aggregated per wavefront: one atomic on the queue's
+// tail reserves the entries of the whole wavefront (ballot + popcount), and
+// each lane writes at the count of entries of the lanes below it (mbcnt).
+__device__ __forceinline__ void queue_append1(const Params &P, int d, bool f, int v)
+{
+    const unsigned long long m = __ballot(f);
+    if (!m) return;
+    unsigned long long base = 0;
+    if (__lane_id() == 0)
+        base = atomicAdd(&P.ctrl->slot[(d + 1) % kSlots].c[0][kQueueTail], (unsigned long long)__popcll(m));
+    base = bcast_u64(base, 0);
+    const long long pos =
+        (long long)base + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    if (f) {
+        if (pos < P.q_cap) queue_of(P, d + 1)[pos] = v;
+        else atomicOr((unsigned *)&P.ctrl->status, 0x400u);
+    }
+}
+
+// The same for up to four entries per lane (entry q of every lane, q = 0..3):
+// one atomic for the wavefront's total; entry q of a lane goes after all
+// entries of index < q and after entry q of the lanes below it.  Only scalar
+// prefix sums and one mbcnt per entry, so it adds few vector registers to
+// the edge loop it runs in.
+__device__ __forceinline__ void queue_append4(const Params &P, int d, const bool (&f)[4], const int (&v)[4])
+{
+    unsigned long long m[4];
+    int pre[4];
+    int total = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        m[q] = __ballot(f[q]);
+        pre[q] = total;
+        total += __popcll(m[q]);
+    }
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (__lane_id() == 0)
+        base = atomicAdd(&P.ctrl->slot[(d + 1) % kSlots].c[0][kQueueTail], (unsigned long long)total);
+    base = bcast_u64(base, 0);
+    int *dst = queue_of(P, d + 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (f[q]) {
+            const long long pos = (long long)base + pre[q] +
+                                  __builtin_amdgcn_mbcnt_hi((unsigned)(m[q] >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)m[q], 0u));
+            if (pos < P.q_cap) dst[pos] = v[q];
+            else atomicOr((unsigned *)&P.ctrl->status, 0x400u);
+        }
+    }
+}
+
+// Bitmap-to-queue conversion of a wavefront task's output words: lane l holds
+// the found-vertex word wbase + l (0 past the task).  Popcount, prefix sum,
+// one atomic for the task's total, then each lane scatters its word's
+// vertices in ascending order, so the task's vertices land ascending.
+__device__ __forceinline__ void queue_append_words(const Params &P, int d, long long wbase, unsigned long long wm)
+{
+    const int lane = __lane_id();
+    const int c = __popcll(wm);
+    const int incl = wave_incl_scan32(c);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&P.ctrl->slot[(d + 1) % kSlots].c[0][kQueueTail], (unsigned long long)total);
+    base = bcast_u64(base, 0);
+    long long pos = (long long)base + incl - c;
+    int *dst = queue_of(P, d + 1);
+    const long long v0 = (wbase + lane) << 6;
+    while (wm) {
+        const int b = __ffsll((long long)wm) - 1;
+        wm &= wm - 1;
+        if (pos < P.q_cap) dst[pos] = (int)(v0 + b);
+        else atomicOr((unsigned *)&P.ctrl->status, 0x400u);
+        ++pos;
+    }
+}
+
+// Where a step appends the hubs it discovers: F_{d+1}'s hub list.
+struct HubSink {
+    const int *deg;
+    unsigned long long *tail;
+    Item *dst;
+    long long cap;
+    unsigned *status;
+    int chunk_log2;
+};
+
+__device__ __forceinline__ HubSink hub_sink(const Params &P, int d)
+{
+    return HubSink{P.deg, &P.ctrl->slot[(d + 1) % kSlots].c[0][kHubTail], hubs_of(P, d + 1), P.hq_cap,
+                   (unsigned *)&P.ctrl->status, P.chunk_log2};
+}
+
+// Hubs discovered inside the edge and probe loops are staged in LDS (one
+// LDS atomic per hub, almost no registers in those loops) and written to the
+// hub list by the whole block once the step is done (hub_flush), with one
+// device atomic per block: appends to one global tail serialise, so they are
+// aggregated as far up as the kernel allows.
+//
+// A list pays only while it is short: a top-down layer whose frontier holds
+// many hubs reads most of the hub table anyway, and such a frontier is
+// usually followed by a bottom-up layer that does not read the list at all.
+// So a list longer than a quarter of the table (all of it for tables under
+// 16384 entries) is abandoned: a block that
+// stages more than kHubStage hubs, or finds the tail already past that
+// limit, only pushes the tail past it, and the consumer then falls back to
+// the table (hub_list_usable).
+constexpr int kHubStage = 256;
+struct HubStage {
+    int n;                           // hubs staged (may exceed kHubStage: abandoned)
+    int tot;                         // their chunks
+    int cur;                         // chunks placed so far
+    int pad;
+    unsigned long long base;         // the block's range of the hub list
+    int v[kHubStage];
+};
+
+// Longest hub list worth keeping (entries).
+__device__ __forceinline__ long long hub_list_limit(const Params &P)
+{
+    return P.hq_cap >= 16384 ? P.hq_cap >> 2 : P.hq_cap;
+}
+
+__device__ __forceinline__ bool hub_list_usable(const Params &P, long long len)
+{
+    return len <= hub_list_limit(P);
+}
+
+__device__ __forceinline__ void hub_stage_reset(HubStage *hs)
+{
+    hs->n = 0;
+    hs->tot = 0;
+    hs->cur = 0;
+}
+
+__device__ __forceinline__ int hub_chunks(const HubSink &S, int v)
+{
+    const long long du = S.deg[v];
+    return (int)((du + (1ll << S.chunk_log2) - 1) >> S.chunk_log2);
+}
+
+__device__ __forceinline__ void hub_stage(HubStage *hs, int v)
+{
+    const int i = atomicAdd(&hs->n, 1);
+    if (i < kHubStage) hs->v[i] = v;
+}
+
+// The block's staged hubs to F_{d+1}'s hub list: their chunks are counted
+// in LDS, one device atomic reserves the block's range, and each wavefront
+// writes the chunks of the hubs it takes.  The stage is empty afterwards.
+// Every thread of the block calls it (it has block barriers).
+__device__ __forceinline__ void hub_flush(const Params &P, HubStage *hs, int d, int nwaves_block)
+{
+    __syncthreads();
+    const int n = hs->n;
+    if (n > 0) {
+        const HubSink S = hub_sink(P, d);
+        const long long limit = hub_list_limit(P);
+        const int lane = __lane_id();
+        if (n <= kHubStage)
+            for (int i = threadIdx.x; i < n; i += nwaves_block * 64) atomicAdd(&hs->tot, hub_chunks(S, hs->v[i]));
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long b = ~0ull;
+            const long long seen = (long long)__hip_atomic_load(S.tail, __ATOMIC_RELAXED, AGENT);
+            if (n > kHubStage || seen > limit) {
+                // abandoned: make sure the tail ends past the limit
+                if (seen <= limit) atomicAdd(S.tail, (unsigned long long)(limit + 1));
+            } else {
+                b = atomicAdd(S.tail, (unsigned long long)hs->tot);
+                if ((long long)b + hs->tot > limit) b = ~0ull;
+            }
+            hs->base = b;
+        }
+        __syncthreads();
+        const unsigned long long base = hs->base;
+        if (base != ~0ull) {
+            for (int i = threadIdx.x >> 6; i < n; i += nwaves_block) {
+                const int u = hs->v[i];
+                const int nk = hub_chunks(S, u);
+                int off = 0;
+                if (lane == 0) off = atomicAdd(&hs->cur, nk);
+                off = __builtin_amdgcn_readlane(off, 0);
+                for (int c = lane; c < nk; c += 64) S.dst[base + off + c] = Item{u, c};
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) hub_stage_reset(hs);
+}
+
+// ---------------------------------------------------------------------------
 // Up to four frontier edges (u_q -> col[j_q]) per lane of a top-down layer.
 // A target v is a candidate when it is in no layer <= d (neither in vis nor
 // in the frontier).  Canonical parent = the minimum frontier neighbour: a plain
@@ -59,7 +256,7 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
                                           const long long (&jq)[4], const bool (&okq)[4],
                                           const unsigned long long *front, unsigned long long *next,
                                           unsigned long long &nf, unsigned long long &mf,
-                                          unsigned long long &nh)
+                                          unsigned long long &nh, HubStage *hs)
 {
     int v[4];
 #pragma unroll
@@ -95,17 +292,23 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
             cand[q] = cand[q] && !(nw[q] & bit);
             ob[q] = cand[q] ? atomicOr(&next[v[q] >> 6], bit) : 0ull;
         }
+        bool win[4];
+        int dvq[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (cand[q] && !((ob[q] >> (v[q] & 63)) & 1ull)) {
+            win[q] = cand[q] && !((ob[q] >> (v[q] & 63)) & 1ull);
+            dvq[q] = 0;
+            if (win[q]) {
                 P.level[v[q]] = d + 1;
                 P.parent[v[q]] = uq[q];
                 nf += 1;
-                const int dv = P.deg[v[q]];
-                mf += (unsigned long long)dv;
-                nh += dv > P.hub_deg;
+                dvq[q] = P.deg[v[q]];
+                mf += (unsigned long long)dvq[q];
+                nh += dvq[q] > P.hub_deg;
+                if (P.hub_list == HL_ALL && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
             }
         }
+        if (P.q_write) queue_append4(P, d, win, v);
         return;
     }
     unsigned pv[4];
@@ -117,98 +320,158 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
         cand[q] = cand[q] && (unsigned)uq[q] < pv[q];
         old[q] = cand[q] ? atomicMin((unsigned int *)&P.parent[v[q]], (unsigned int)uq[q]) : 0u;
     }
+    bool win[4];
+    int dvq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (cand[q] && old[q] == 0xFFFFFFFFu) {
+        win[q] = cand[q] && old[q] == 0xFFFFFFFFu;
+        dvq[q] = 0;
+        if (win[q]) {
             P.level[v[q]] = d + 1;
             atomicOr(&next[v[q] >> 6], 1ull << (v[q] & 63));
             nf += 1;
-            const int dv = P.deg[v[q]];
-            mf += (unsigned long long)dv;
-            nh += dv > P.hub_deg;
+            dvq[q] = P.deg[v[q]];
+            mf += (unsigned long long)dvq[q];
+            nh += dvq[q] > P.hub_deg;
+            if (P.hub_list == HL_ALL && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
         }
+    }
+    if (P.q_write) queue_append4(P, d, win, v);
+}
+
+// Where a top-down layer finds its frontier F_d: the bitmap (scanned) or the
+// queue the layer before wrote; and F_d's vertices above hub_deg: the list of
+// their chunks the layer before wrote, or the graph's whole table of hub
+// chunks, each tested against the frontier bitmap.
+struct FrontSrc {
+    const int *q;          // F_d as a queue, or nullptr: scan the bitmap
+    long long qlen;
+    bool q_fold;           // queue entries still have to join vis
+    const Item *hubs;      // hub chunks to look at
+    long long nhubs;       // their number (0: no hub in the frontier)
+    bool hubs_listed;      // `hubs` lists only frontier hubs
+};
+
+// The edges of the lanes' vertices (u, degree dl, row start sl; dl = 0 for no
+// vertex) laid end to end (prefix sum of degrees + shuffle binary search) and
+// handed to the sink 256 per round, four per lane.
+template <class Sink>
+__device__ __forceinline__ void td_expand(const Params &P, int u, int dl, long long sl, Sink &sink)
+{
+    const int lane = __lane_id();
+    const int incl = wave_incl_scan32(dl);
+    const int ex = incl - dl;
+    const int E = __builtin_amdgcn_readlane(incl, 63);
+    for (int r0 = 0; r0 < E; r0 += 256) {
+        int uq[4];
+        long long jq[4];
+        bool okq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = r0 + q * 64 + lane;
+            okq[q] = idx < E;
+            const int lo = lane_search(ex, idx);
+            uq[q] = __shfl(u, lo);
+            jq[q] = __shfl(sl, lo) + (idx - __shfl(ex, lo));
+        }
+        sink(uq, jq, okq);
     }
 }
 
 // Top-down edge enumeration (Algorithm 1's two loops).
-//  * A wavefront task covers G bitmap words.  The task's frontier vertices are
-//    laid out over the lanes (64 per round, found by a prefix sum of the
-//    words' popcounts and a select of the set bit), and the edges of those
-//    vertices are laid end to end (prefix sum of their degrees) and expanded
-//    256 per round, four per lane: the work of a task is balanced over the
-//    lanes whatever the degree mix, and its dependent loads are shared.
-//  * Vertices of degree > hub_deg are expanded through the static table of
-//    their 2^chunk_log2-edge chunks, 64 table entries per wavefront step, so a
-//    hub's edges spread over the whole grid.
+//  * From the bitmap: a wavefront task covers G bitmap words.  The task's
+//    frontier vertices are laid out over the lanes (64 per round, found by a
+//    prefix sum of the words' popcounts and a select of the set bit): the
+//    bitmap-to-queue conversion of the frontier, done per wavefront in
+//    registers.
+//  * From a queue: a task is E <= 64 consecutive entries, E sized so that the
+//    tasks spread over the whole grid even for a small frontier.
+//  Either way the edges of a round's vertices are expanded end to end
+//  (td_expand), so the work of a task is balanced over the lanes whatever
+//  the degree mix, and its dependent loads are shared.
+//  * Vertices of degree > hub_deg are expanded chunk by chunk (2^chunk_log2
+//    edges), 64 chunks per wavefront step, so a hub's edges spread over the
+//    whole grid: from the list of the frontier's hubs, or from the table of
+//    every hub chunk of the graph, keeping the chunks of frontier vertices.
 // sink(uq, jq, okq) receives four (source, edge index) pairs per lane, with
 // every lane of the wavefront active; okq marks the real ones.  The
-// assignment of edges to wavefronts depends only on the frontier, so passes
-// over the same frontier see the same edges in the same wavefronts.
+// assignment of edges to wavefronts depends only on the frontier and its
+// sources, so passes over the same frontier see the same edges in the same
+// wavefronts.
 template <class Sink>
-__device__ void td_scan(const Params &P, const unsigned long long *front, bool hubs_in_front, bool fold_vis,
+__device__ __forceinline__ void td_scan(const Params &P, const unsigned long long *front, const FrontSrc &src, bool fold_vis,
                         long long gwave, long long nwaves, Sink &sink)
 {
     const int lane = __lane_id();
-    const int G = P.wpg_td;
-    for (long long base = gwave * G; base < P.W; base += nwaves * G) {
-        const long long myw = base + lane;
-        const unsigned long long fwl = (lane < G && myw < P.W) ? front[myw] : 0ull;
-        if (fold_vis && fwl) P.vis[myw] |= fwl;  // F_d joins the finished layers (lane owns word)
-        const int cnt = __popcll(fwl);
-        const int cincl = wave_incl_scan32(cnt);
-        const int cex = cincl - cnt;
-        const int V = __builtin_amdgcn_readlane(cincl, 63);
-        for (int vr = 0; vr < V; vr += 64) {
-            // cross-lane reads run with every lane active (an inactive source
-            // lane would read as 0); only lanes with vi < V use the result
-            const int vi = vr + lane;
-            const bool vok = vi < V;
-            const int l = lane_search(cex, vok ? vi : 0);
-            const unsigned long long fw = (unsigned long long)__shfl((long long)fwl, l);
-            const int kth = vi - __shfl(cex, l);
+    if (src.q) {
+        const long long len = src.qlen;
+        long long E = (len + nwaves - 1) / nwaves;
+        E = E < 1 ? 1 : (E > 64 ? 64 : E);
+        for (long long lo = gwave * E; lo < len; lo += nwaves * E) {
             int u = -1, dl = 0;
             long long sl = 0;
-            if (vok) {
-                u = (int)(((base + l) << 6) + select_bit(fw, kth));
+            if (lane < E && lo + lane < len) {
+                u = src.q[lo + lane];
                 if ((unsigned)u >= (unsigned)P.n) {   // would be a kernel bug: report it
                     atomicOr((unsigned *)&P.ctrl->status, 8u);
-                    u = 0;
+                    u = -1;
+                } else {
+                    // F_d joins the finished layers (other lanes may share the word)
+                    if (fold_vis && src.q_fold) atomicOr(&P.vis[u >> 6], 1ull << (u & 63));
+                    dl = P.deg[u];
+                    sl = P.off[u];
+                    if (dl > P.hub_deg) dl = 0;      // expanded chunk by chunk below
                 }
-                dl = P.deg[u];
-                sl = P.off[u];
-                if (dl > P.hub_deg) dl = 0;      // expanded through the hub table
             }
-            const int incl = wave_incl_scan32(dl);
-            const int ex = incl - dl;
-            const int E = __builtin_amdgcn_readlane(incl, 63);
-            for (int r0 = 0; r0 < E; r0 += 256) {
-                int uq[4];
-                long long jq[4];
-                bool okq[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int idx = r0 + q * 64 + lane;
-                    okq[q] = idx < E;
-                    const int lo = lane_search(ex, idx);
-                    uq[q] = __shfl(u, lo);
-                    jq[q] = __shfl(sl, lo) + (idx - __shfl(ex, lo));
+            td_expand(P, u, dl, sl, sink);
+        }
+    } else {
+        const int G = P.wpg_td;
+        for (long long base = gwave * G; base < P.W; base += nwaves * G) {
+            const long long myw = base + lane;
+            const unsigned long long fwl = (lane < G && myw < P.W) ? front[myw] : 0ull;
+            if (fold_vis && fwl) P.vis[myw] |= fwl;  // F_d joins the finished layers (lane owns word)
+            const int cnt = __popcll(fwl);
+            const int cincl = wave_incl_scan32(cnt);
+            const int cex = cincl - cnt;
+            const int V = __builtin_amdgcn_readlane(cincl, 63);
+            for (int vr = 0; vr < V; vr += 64) {
+                // cross-lane reads run with every lane active (an inactive source
+                // lane would read as 0); only lanes with vi < V use the result
+                const int vi = vr + lane;
+                const bool vok = vi < V;
+                const int l = lane_search(cex, vok ? vi : 0);
+                const unsigned long long fw = (unsigned long long)__shfl((long long)fwl, l);
+                const int kth = vi - __shfl(cex, l);
+                int u = -1, dl = 0;
+                long long sl = 0;
+                if (vok) {
+                    u = (int)(((base + l) << 6) + select_bit(fw, kth));
+                    if ((unsigned)u >= (unsigned)P.n) {   // would be a kernel bug: report it
+                        atomicOr((unsigned *)&P.ctrl->status, 8u);
+                        u = 0;
+                    }
+                    dl = P.deg[u];
+                    sl = P.off[u];
+                    if (dl > P.hub_deg) dl = 0;      // expanded chunk by chunk below
                 }
-                sink(uq, jq, okq);
+                td_expand(P, u, dl, sl, sink);
             }
         }
     }
-    // high-degree frontier vertices: the hub chunk table, 64 entries per step,
-    // lane l of wavefront g taking entry g + l * nwaves so that the adjacent
-    // chunks of one hub go to different wavefronts
+    // high-degree frontier vertices, 64 chunks per step, lane l of wavefront g
+    // taking entry g + l * nwaves so that the adjacent chunks of one hub go to
+    // different wavefronts
     const long long CH = 1ll << P.chunk_log2;
-    const long long n_hub = hubs_in_front ? P.n_hub : 0;   // nothing to find otherwise
-    for (long long b0 = gwave; b0 < n_hub; b0 += nwaves * 64) {
+    const long long nh = src.nhubs;
+    for (long long b0 = gwave; b0 < nh; b0 += nwaves * 64) {
         const long long idx = b0 + (long long)lane * nwaves;
         Item it{-1, 0};
-        if (idx < P.n_hub) it = P.hub[idx];
+        if (idx < nh) it = src.hubs[idx];
         // the table lists every vertex above the graph's cut-off; a vertex at
         // or below this run's cut-off was expanded with the flattened edges
-        const bool hit = it.u >= 0 && test_bit(front, it.u) && P.deg[it.u] > P.hub_deg;
+        const bool hit =
+            it.u >= 0 && (src.hubs_listed || (test_bit(front, it.u) && P.deg[it.u] > P.hub_deg));
         unsigned long long m = __ballot(hit);
         while (m) {
             const int k = __ffsll((long long)m) - 1;
@@ -234,15 +497,15 @@ __device__ void td_scan(const Params &P, const unsigned long long *front, bool h
 }
 
 // Top-down step (Algorithm 1) with canonical parents by atomic minimum.
-__device__ void top_down_step(const Params &P, int d, const unsigned long long *front,
+__device__ __forceinline__ void top_down_step(const Params &P, int d, const unsigned long long *front,
                               unsigned long long *next, unsigned long long &nf,
-                              unsigned long long &mf, unsigned long long &nh, bool hubs_in_front,
-                              long long gwave, long long nwaves)
+                              unsigned long long &mf, unsigned long long &nh, const FrontSrc &src,
+                              long long gwave, long long nwaves, HubStage *hs)
 {
     auto sink = [&](const int (&uq)[4], const long long (&jq)[4], const bool (&okq)[4]) {
-        td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh);
+        td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh, hs);
     };
-    td_scan(P, front, hubs_in_front, true, gwave, nwaves, sink);
+    td_scan(P, front, src, true, gwave, nwaves, sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -329,10 +592,10 @@ __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned
     }
 }
 
-__device__ void bottom_up_step(const Params &P, int d, const unsigned long long *front,
+__device__ __forceinline__ void bottom_up_step(const Params &P, int d, const unsigned long long *front,
                                unsigned long long *next, unsigned long long &nf,
                                unsigned long long &mf, unsigned long long &nh, long long gwave,
-                               long long nwaves)
+                               long long nwaves, HubStage *hs)
 {
     const int lane = __lane_id();
     const int K = P.probe_k;
@@ -349,6 +612,7 @@ __device__ void bottom_up_step(const Params &P, int d, const unsigned long long 
         // fully seen words only need the frontier folded into vis
         if (inr && (fwl & ~vwl) && ((vwl | fwl) == ~0ull)) P.vis[myw] = vwl | fwl;
         unsigned long long todo = __ballot((vwl | fwl) != ~0ull);
+        unsigned long long tfm = 0;   // lane l: vertices found in word base + l
         while (todo) {
             int wi[2];
             wi[0] = __ffsll((long long)todo) - 1;
@@ -414,7 +678,9 @@ __device__ void bottom_up_step(const Params &P, int d, const unsigned long long 
                     nf += 1;
                     mf += (unsigned long long)dg[j];
                     nh += dg[j] > P.hub_deg;
+                    if (P.hub_list == HL_ALL && dg[j] > P.hub_deg) hub_stage(hs, (int)v[j]);
                 }
+                if (lane == wi[j]) tfm = fm;
                 // `next` was cleared one layer ahead: store only nonzero words
                 if (lane == 0) {
                     const long long w = base + wi[j];
@@ -423,11 +689,13 @@ __device__ void bottom_up_step(const Params &P, int d, const unsigned long long 
                 }
             }
         }
+        // the task's part of F_{d+1} as a queue, in ascending order
+        if (P.q_write) queue_append_words(P, d, base, tfm);
     }
 }
 
 // ---------------------------------------------------------------------------
-__device__ void flush_counters(unsigned long long nf, unsigned long long mf, unsigned long long nh,
+__device__ __forceinline__ void flush_counters(unsigned long long nf, unsigned long long mf, unsigned long long nh,
                                Slot *slot, unsigned long long *s_red, int nwaves_block)
 {
     unsigned long long *sub = slot->c[blockIdx.x % kSub];
@@ -471,8 +739,8 @@ __device__ void flush_counters(unsigned long long nf, unsigned long long mf, uns
 //           (block, tile), pairs placed by LDS atomics;
 //   reduce  : per tile, minima in LDS over unvisited targets, then output.
 
-static __device__ void bin_count_pass(const Params &P, const unsigned long long *front, unsigned *hist,
-                                      bool hubs_in_front, long long gwave, long long nwaves)
+static __device__ __forceinline__ void bin_count_pass(const Params &P, const unsigned long long *front, unsigned *hist,
+                                      const FrontSrc &src, long long gwave, long long nwaves)
 {
     for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) hist[b] = 0u;
     __syncthreads();
@@ -487,7 +755,7 @@ static __device__ void bin_count_pass(const Params &P, const unsigned long long 
             atomicAdd(&hist[P.col[jq[q]] >> P.bin_log2], 1u);
         }
     };
-    td_scan(P, front, hubs_in_front, true, gwave, nwaves, sink);
+    td_scan(P, front, src, true, gwave, nwaves, sink);
     __syncthreads();
     for (int b = threadIdx.x; b < P.nbins; b += blockDim.x)
         if (hist[b]) atomicAdd(&P.bin_cnt[b], (int)hist[b]);
@@ -503,15 +771,23 @@ struct LayerView {
     int *parent;
     LayerState S;
     long long n_f, m_f, n_h;
+    long long q_len, hq_len;         // entries of F_d's queue and hub list
 };
 
-__device__ bool run_layer(const Params &Pin, int parity, long long gwave, long long nwaves,
+// kLists: the build that keeps frontier queues and hub lists (the options
+// td_queue and td_hub_list) and reads them; the other build has none of
+// their code, so the plain bitmap path pays no registers for them.  With
+// hub lists for layer 1 only, layer 1 runs in the list build and the other
+// layers in the plain one.
+template <bool kLists>
+__device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long long gwave, long long nwaves,
                           long long gt, long long nt, bool leader, unsigned long long *s_red,
                           int nwaves_block, LayerView *view, bool same_kernel, int d_hint,
-                          unsigned *hist, bool allow_binned)
+                          unsigned *hist, bool allow_binned, HubStage *hs)
 {
     Ctrl *C = Pin.ctrl;
     if (threadIdx.x == 0) {
+        hub_stage_reset(hs);
         view->done = C->done;
         view->level = C->level;
         view->parent = C->parent;
@@ -530,6 +806,8 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
         view->n_f = a;
         view->m_f = b;
         view->n_h = c;
+        view->q_len = (long long)(same_kernel ? ld_relaxed(&sl.c[0][kQueueTail]) : sl.c[0][kQueueTail]);
+        view->hq_len = (long long)(same_kernel ? ld_relaxed(&sl.c[0][kHubTail]) : sl.c[0][kHubTail]);
     }
     __syncthreads();
     if (view->done) return false;
@@ -537,6 +815,10 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
     Params P = Pin;
     P.level = view->level;
     P.parent = view->parent;
+    if (!kLists) {
+        P.td_queue = QM_OFF;
+        P.hub_list = 0;
+    }
     const LayerState S = view->S;
     const int d = S.d;
     if (d_hint >= 0 && d != d_hint) {
@@ -567,8 +849,37 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
     // a large top-down layer is bucketed by destination tile when the three
     // binned kernels follow this one (every block decides the same)
     const bool binned = allow_binned && cur == DIR_TD && m_f >= P.bin_min_edges && m_f <= P.bin_cap;
+    // where a top-down step finds F_d and its hubs
+    FrontSrc src;
+    src.q = nullptr;
+    src.qlen = 0;
+    src.q_fold = false;
+    if (P.td_queue != QM_OFF && S.qform != QF_NONE) {
+        if (view->q_len == n_f && n_f <= P.q_cap) {
+            src.q = queue_of(P, d);
+            src.qlen = n_f;
+            src.q_fold = S.qform == QF_LIST;
+        } else if (leader) {
+            // every producer appends each vertex it discovers once: a queue
+            // whose length differs from the frontier count is a kernel bug
+            atomicOr((unsigned *)&C->status, 0x1000u);
+        }
+    }
+    if (kLists && S.hlist && hub_list_usable(P, view->hq_len)) {
+        src.hubs = hubs_of(P, d);
+        src.nhubs = view->hq_len;
+        src.hubs_listed = true;
+    } else {
+        src.hubs = P.hub;
+        src.nhubs = view->n_h > 0 ? P.n_hub : 0;
+        src.hubs_listed = false;
+    }
+    // this layer also writes F_{d+1} as a queue
+    P.q_write = P.td_queue == QM_ALL || (P.td_queue == QM_TOPDOWN && cur == DIR_TD && !binned);
     if (leader) {
         C->bin_layer = binned ? d : -1;
+        C->bin_qlen = src.q ? (int)src.qlen : -1;
+        C->bin_hlist = src.hubs_listed;
         if (d < P.trace_cap) {
             LayerRec r;
             r.dir = cur;
@@ -590,6 +901,9 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
         Nx.v_u = v_u;
         Nx.reached = S.reached + n_f;
         Nx.reached_deg = S.reached_deg + m_f;
+        // the bottom-up step writes its found vertices into vis itself
+        Nx.qform = !P.q_write ? QF_NONE : (cur == DIR_BU ? QF_LIST_VIS : QF_LIST);
+        Nx.hlist = P.hub_list == HL_ALL;     // every step of this layer lists its hubs
         C->st[parity ^ 1] = Nx;
         C->parity = parity ^ 1;
         Slot *Z = &C->slot[(d + 2) % kSlots];
@@ -598,14 +912,17 @@ __device__ bool run_layer(const Params &Pin, int parity, long long gwave, long l
             Z->c[k][1] = 0;
             Z->c[k][2] = 0;
         }
+        Z->c[0][kHubTail] = 0;
+        Z->c[0][kQueueTail] = 0;
     }
     unsigned long long *front = P.bm + (long long)(d % 3) * P.W;
     unsigned long long *next = P.bm + (long long)((d + 1) % 3) * P.W;
     unsigned long long *spare = P.bm + (long long)((d + 2) % 3) * P.W;
     unsigned long long nf = 0, mf = 0, nh = 0;
-    if (binned) bin_count_pass(P, front, hist, view->n_h > 0, gwave, nwaves);
-    else if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, view->n_h > 0, gwave, nwaves);
-    else bottom_up_step(P, d, front, next, nf, mf, nh, gwave, nwaves);
+    if (binned) bin_count_pass(P, front, hist, src, gwave, nwaves);
+    else if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, src, gwave, nwaves, hs);
+    else bottom_up_step(P, d, front, next, nf, mf, nh, gwave, nwaves, hs);
+    if (P.hub_list == HL_ALL) hub_flush(P, hs, d, nwaves_block);
     for (long long w = gt; w < P.W; w += nt) spare[w] = 0ull;   // `next` of layer d+1
     flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, nwaves_block);
     return true;
@@ -646,9 +963,13 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
         P.bm[w] = rb;                        // F_0 = {root}
         P.bm[P.W + w] = 0ull;                // next of layer 0
     }
+    const long long deg_r = P.off[root + 1] - P.off[root];
+    const bool root_hub = P.hub_list != HL_OFF && deg_r > P.hub_deg;
+    long long root_chunks = root_hub ? (deg_r + (1ll << P.chunk_log2) - 1) >> P.chunk_log2 : 0;
+    if (root_chunks > hub_list_limit(P)) root_chunks = -1;   // too long: layer 0 scans the table
+    for (long long c = gt; c < root_chunks; c += nt) hubs_of(P, 0)[c] = Item{root, (int)c};   // F_0's hub list
     if (gt == 0) {
         Ctrl *C = P.ctrl;
-        const long long deg_r = P.off[root + 1] - P.off[root];
         C->async_run = P.async_run;
         C->fail_injected = P.fail_injected;
         C->level = P.level;
@@ -666,38 +987,48 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
         S.v_u = P.n;
         S.reached = 0;
         S.reached_deg = 0;
-        S.pad[0] = S.pad[1] = S.pad[2] = 0;
+        S.qform = P.td_queue != QM_OFF ? QF_LIST : QF_NONE;
+        S.hlist = P.hub_list != HL_OFF && root_chunks >= 0;
+        S.pad[0] = S.pad[1] = 0;
         C->st[0] = S;
         C->st[1] = S;
         C->status = 0;
+        if (P.td_queue != QM_OFF) queue_of(P, 0)[0] = root;   // F_0 as a queue
         for (int k = 0; k < kSlots; ++k)
-            for (int j = 0; j < kSub; ++j) {
-                C->slot[k].c[j][0] = (k == 0 && j == 0) ? 1ull : 0ull;
-                C->slot[k].c[j][1] = (k == 0 && j == 0) ? (unsigned long long)deg_r : 0ull;
-                C->slot[k].c[j][2] = (k == 0 && j == 0 && deg_r > P.hub_deg) ? 1ull : 0ull;
-            }
+            for (int j = 0; j < kSub; ++j)
+                for (int e = 0; e < 8; ++e) C->slot[k].c[j][e] = 0ull;
+        C->slot[0].c[0][0] = 1ull;
+        C->slot[0].c[0][1] = (unsigned long long)deg_r;
+        C->slot[0].c[0][2] = deg_r > P.hub_deg ? 1ull : 0ull;
+        C->slot[0].c[0][kQueueTail] = P.td_queue != QM_OFF ? 1ull : 0ull;
+        C->slot[0].c[0][kHubTail] =
+            root_chunks < 0 ? (unsigned long long)hub_list_limit(P) + 1 : (unsigned long long)root_chunks;
     }
 }
 
 // One layer over the whole grid; the body of both builds of the layer kernel.
+template <bool kLists>
 __device__ __forceinline__ void layer_grid(const Params &P, int layer, int allow_binned,
-                                           unsigned long long *s_red, LayerView *view, unsigned *hist)
+                                           unsigned long long *s_red, LayerView *view, unsigned *hist,
+                                           HubStage *hs)
 {
     const int parity = layer & 1;
     const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
-    run_layer(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
-              kWavesPerBlock, view, false, layer, hist, allow_binned != 0 && P.nbins <= kMaxBins);
+    run_layer<kLists>(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
+              kWavesPerBlock, view, false, layer, hist, allow_binned != 0 && P.nbins <= kMaxBins, hs);
 }
 
+template <bool kLists>
 __global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, int allow_binned)
 {
     __shared__ unsigned long long s_red[3 * kWavesPerBlock];
     __shared__ LayerView view;
     __shared__ unsigned hist[kMaxBins];
-    layer_grid(P, layer, allow_binned, s_red, &view, hist);
+    __shared__ HubStage hs;
+    layer_grid<kLists>(P, layer, allow_binned, s_red, &view, hist, &hs);
 }
 
 // The same kernel built for kWideWavesPerSimd resident wavefronts per SIMD:
@@ -705,29 +1036,33 @@ __global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, 
 // whose frontier bitmap no longer fits the L2, the layers are chains of
 // dependent probes and row loads, and more chains in flight win; on smaller
 // graphs the spills cost more than the extra wavefronts gain.
+template <bool kLists>
 __global__ void __launch_bounds__(kBlock, kWideWavesPerSimd) bfs_layer_kernel_wide(Params P, int layer,
                                                                                   int allow_binned)
 {
     __shared__ unsigned long long s_red[3 * kWavesPerBlock];
     __shared__ LayerView view;
     __shared__ unsigned hist[kMaxBins];
-    layer_grid(P, layer, allow_binned, s_red, &view, hist);
+    __shared__ HubStage hs;
+    layer_grid<kLists>(P, layer, allow_binned, s_red, &view, hist, &hs);
 }
 
 // One block runs whatever layers remain, with block barriers between them.
+template <bool kLists>
 __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
 {
     __shared__ unsigned long long s_red[3 * (kFinishBlock / 64)];
     __shared__ int s_parity;
     __shared__ LayerView view;
+    __shared__ HubStage hs;
     const long long gwave = threadIdx.x >> 6;
     const long long nwaves = kFinishBlock / 64;
     for (;;) {
         if (threadIdx.x == 0) s_parity = P.ctrl->parity;
         __syncthreads();
         const int parity = s_parity;
-        if (!run_layer(P, parity, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, s_red,
-                       kFinishBlock / 64, &view, true, -1, nullptr, false))
+        if (!run_layer<kLists>(P, parity, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, s_red,
+                       kFinishBlock / 64, &view, true, -1, nullptr, false, &hs))
             break;
         __syncthreads();
     }
@@ -782,21 +1117,34 @@ __global__ void __launch_bounds__(kBlock) bfs_bin_scatter_kernel(Params P, int l
 {
     __shared__ unsigned lbase[kMaxBins];
     __shared__ int s_go;
-    __shared__ unsigned long long s_hubs;
+    __shared__ int s_qlen;
+    __shared__ int s_hlist;
+    __shared__ unsigned long long s_hubs, s_hq;
     Ctrl *C = P.ctrl;
     if (threadIdx.x == 0) {
         s_go = C->bin_layer == layer && P.nbins <= kMaxBins;
+        s_qlen = C->bin_qlen;
         unsigned long long h = 0;
         const Slot &sl = C->slot[layer % kSlots];
         for (int k = 0; k < kSub; ++k) h += sl.c[k][2];
         s_hubs = h;
+        s_hq = sl.c[0][kHubTail];
+        s_hlist = C->bin_hlist;
     }
     __syncthreads();
     if (!s_go) return;
     const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
     const unsigned long long *front = P.bm + (long long)(layer % 3) * P.W;
-    const bool hubs = s_hubs > 0;
+    // the frontier sources the layer kernel's count pass used
+    FrontSrc src;
+    src.q = s_qlen >= 0 ? queue_of(P, layer) : nullptr;
+    src.qlen = s_qlen >= 0 ? s_qlen : 0;
+    src.q_fold = false;
+    const bool listed = s_hlist && hub_list_usable(P, (long long)s_hq);
+    src.hubs = listed ? hubs_of(P, layer) : P.hub;
+    src.nhubs = listed ? (long long)s_hq : (s_hubs > 0 ? P.n_hub : 0);
+    src.hubs_listed = listed;
     // this block's edges per tile, then a range of each bucket for them
     for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) lbase[b] = 0u;
     __syncthreads();
@@ -806,7 +1154,7 @@ __global__ void __launch_bounds__(kBlock) bfs_bin_scatter_kernel(Params P, int l
             if (okq[q] && (unsigned long long)jq[q] < (unsigned long long)P.nnz)
                 atomicAdd(&lbase[P.col[jq[q]] >> P.bin_log2], 1u);
     };
-    td_scan(P, front, hubs, false, gwave, nwaves, count);
+    td_scan(P, front, src, false, gwave, nwaves, count);
     __syncthreads();
     for (int b = threadIdx.x; b < P.nbins; b += blockDim.x) {
         const unsigned c = lbase[b];
@@ -827,7 +1175,7 @@ __global__ void __launch_bounds__(kBlock) bfs_bin_scatter_kernel(Params P, int l
                 atomicOr((unsigned *)&C->status, 64u);
         }
     };
-    td_scan(P, front, hubs, false, gwave, nwaves, place);
+    td_scan(P, front, src, false, gwave, nwaves, place);
 }
 
 // Two blocks of this size and their 64 KiB tiles fit one CU, so one tile's
@@ -845,11 +1193,13 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
     __shared__ int s_go;
     __shared__ int *s_level;
     __shared__ int *s_parent;
+    __shared__ HubStage hs;
     Ctrl *C = P.ctrl;
     if (threadIdx.x == 0) {
         s_go = C->bin_layer == layer && P.bin_log2 == kBinLog2;
         s_level = C->level;
         s_parent = C->parent;
+        hub_stage_reset(&hs);
     }
     __syncthreads();
     if (!s_go) return;
@@ -913,10 +1263,18 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
                     mf += (unsigned long long)dv[q];
                     nh += dv[q] > P.hub_deg;
                 }
+                if (P.hub_list == HL_ALL && found[q] && dv[q] > P.hub_deg) hub_stage(&hs, (int)v[q]);
+            }
+            if (P.td_queue == QM_ALL) {
+                int vq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) vq[q] = (int)v[q];
+                queue_append4(P, d, found, vq);
             }
         }
         __syncthreads();
     }
+    if (P.hub_list == HL_ALL) hub_flush(P, &hs, d, kReduceBlock / 64);
     flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, kReduceBlock / 64);
 }
 
@@ -951,6 +1309,8 @@ __device__ void layer0_state(const Params &P, Ctrl *C, const LayerState &S, long
     Nx.v_u = v_u;
     Nx.reached = 1;
     Nx.reached_deg = deg_r;
+    Nx.qform = P.td_queue != QM_OFF ? QF_LIST : QF_NONE;   // F_1 is appended to its queue
+    Nx.hlist = P.hub_list != HL_OFF;                        // and its hubs to its hub list
     C->st[1] = Nx;
     C->parity = 1;
 }
@@ -967,7 +1327,9 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
 {
     __shared__ unsigned long long s_next[kFuseWords];
     __shared__ unsigned long long s_red[3 * kWavesPerBlock];
+    __shared__ HubStage hs;
     Ctrl *C = P.ctrl;
+    if (threadIdx.x == 0) hub_stage_reset(&hs);
     const int root = P.root;
     const long long rw = root >> 6;
     const unsigned long long rbit = 1ull << (root & 63);
@@ -1010,20 +1372,33 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
     }
     __syncthreads();   // the range's -1 entries precede its layer-1 entries
     unsigned long long nf = 0, mf = 0, nh = 0;
-    for (long long j = s0 + threadIdx.x; j < e0; j += kBlock) {
-        const int v = P.col[j];
-        if (v == root || v < v0 || v >= v1) continue;
-        const unsigned long long bit = 1ull << (v & 63);
-        const unsigned long long old = atomicOr(&s_next[(v >> 6) - w0], bit);   // LDS: repeated entries count once
-        if (!(old & bit)) {
-            P.level[v] = 1;
-            P.parent[v] = root;
-            const int dv = P.deg[v];
-            nf += 1;
-            mf += (unsigned long long)dv;
-            nh += dv > P.hub_deg;
+    const int lane = __lane_id();
+    // whole wavefronts step through the row together (the appends to F_1's
+    // queue and hub list are per wavefront)
+    for (long long jb = s0 + (threadIdx.x - lane); jb < e0; jb += kBlock) {
+        const long long j = jb + lane;
+        bool disc = false;
+        int v = -1, dv = 0;
+        if (j < e0) {
+            v = P.col[j];
+            if (v != root && v >= v0 && v < v1) {
+                const unsigned long long bit = 1ull << (v & 63);
+                const unsigned long long old = atomicOr(&s_next[(v >> 6) - w0], bit);   // LDS: repeated entries count once
+                if (!(old & bit)) {
+                    disc = true;
+                    P.level[v] = 1;
+                    P.parent[v] = root;
+                    dv = P.deg[v];
+                    nf += 1;
+                    mf += (unsigned long long)dv;
+                    nh += dv > P.hub_deg;
+                }
+            }
         }
+        if (P.td_queue != QM_OFF) queue_append1(P, 0, disc, v);
+        if (P.hub_list != HL_OFF && disc && dv > P.hub_deg) hub_stage(&hs, v);
     }
+    if (P.hub_list != HL_OFF) hub_flush(P, &hs, 0, kWavesPerBlock);
     __syncthreads();
     for (long long w = w0 + threadIdx.x; w < w1; w += kBlock) P.bm[P.W + w] = s_next[w - w0];   // F_1
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1035,7 +1410,9 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
         S.v_u = P.n;
         S.reached = 0;
         S.reached_deg = 0;
-        S.pad[0] = S.pad[1] = S.pad[2] = 0;
+        S.qform = QF_NONE;
+        S.hlist = 0;
+        S.pad[0] = S.pad[1] = 0;
         C->level = P.level;
         C->parent = P.parent;
         C->root = root;
@@ -1055,7 +1432,10 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
 __global__ void __launch_bounds__(kFinishBlock) bfs_root_kernel(Params P)
 {
     __shared__ unsigned long long s_red[3 * (kFinishBlock / 64)];
+    __shared__ HubStage hs;
     Ctrl *C = P.ctrl;
+    if (threadIdx.x == 0) hub_stage_reset(&hs);
+    __syncthreads();
     const int root = P.root;
     const long long s0 = P.off[root], e0 = P.off[root + 1];
     const long long deg_r = e0 - s0;
@@ -1066,20 +1446,31 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_root_kernel(Params P)
     for (long long w = threadIdx.x; w < P.W; w += kFinishBlock) P.bm[2 * P.W + w] = 0ull;   // `next` of layer 1
     unsigned long long *next = P.bm + P.W;
     unsigned long long nf = 0, mf = 0, nh = 0;
-    for (long long j = s0 + threadIdx.x; j < e0; j += kFinishBlock) {
-        const int v = P.col[j];
-        if (v == root || (unsigned)v >= (unsigned)P.n) continue;
-        const unsigned long long bit = 1ull << (v & 63);
-        const unsigned long long old = atomicOr(&next[v >> 6], bit);
-        if (!(old & bit)) {
-            P.level[v] = 1;
-            P.parent[v] = root;
-            const int dv = P.deg[v];
-            nf += 1;
-            mf += (unsigned long long)dv;
-            nh += dv > P.hub_deg;
+    const int lane = __lane_id();
+    for (long long jb = s0 + (threadIdx.x - lane); jb < e0; jb += kFinishBlock) {
+        const long long j = jb + lane;
+        bool disc = false;
+        int v = -1, dv = 0;
+        if (j < e0) {
+            v = P.col[j];
+            if (v != root && (unsigned)v < (unsigned)P.n) {
+                const unsigned long long bit = 1ull << (v & 63);
+                const unsigned long long old = atomicOr(&next[v >> 6], bit);
+                if (!(old & bit)) {
+                    disc = true;
+                    P.level[v] = 1;
+                    P.parent[v] = root;
+                    dv = P.deg[v];
+                    nf += 1;
+                    mf += (unsigned long long)dv;
+                    nh += dv > P.hub_deg;
+                }
+            }
         }
+        if (P.td_queue != QM_OFF) queue_append1(P, 0, disc, v);
+        if (P.hub_list != HL_OFF && disc && dv > P.hub_deg) hub_stage(&hs, v);
     }
+    if (P.hub_list != HL_OFF) hub_flush(P, &hs, 0, kFinishBlock / 64);
     flush_counters(nf, mf, nh, &C->slot[1], s_red, kFinishBlock / 64);
 }
 
@@ -1103,12 +1494,22 @@ hipError_t launch_init(const Params &p, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
+bool layer_uses_lists(const Params &p, int layer)
+{
+    return p.td_queue != QM_OFF || p.hub_list == HL_ALL || (p.hub_list == HL_LAYER0 && layer == 1);
+}
+
 hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s)
 {
-    if (p.wide)
-        hipLaunchKernelGGL(bfs_layer_kernel_wide, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    const bool lists = layer_uses_lists(p, layer);
+    if (p.wide && lists)
+        hipLaunchKernelGGL(bfs_layer_kernel_wide<true>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    else if (p.wide)
+        hipLaunchKernelGGL(bfs_layer_kernel_wide<false>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    else if (lists)
+        hipLaunchKernelGGL(bfs_layer_kernel<true>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
     else
-        hipLaunchKernelGGL(bfs_layer_kernel, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+        hipLaunchKernelGGL(bfs_layer_kernel<false>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
     return hipGetLastError();
 }
 
@@ -1144,7 +1545,9 @@ hipError_t launch_root(const Params &p, hipStream_t s)
 
 hipError_t launch_finish(const Params &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(bfs_finish_kernel, dim3(1), dim3(kFinishBlock), 0, s, p);
+    if (p.td_queue != QM_OFF || p.hub_list == HL_ALL)
+        hipLaunchKernelGGL(bfs_finish_kernel<true>, dim3(1), dim3(kFinishBlock), 0, s, p);
+    else hipLaunchKernelGGL(bfs_finish_kernel<false>, dim3(1), dim3(kFinishBlock), 0, s, p);
     return hipGetLastError();
 }
 
@@ -1158,15 +1561,22 @@ hipError_t launch_iso_template(const long long *off, long long n, long long W,
 }
 
 void *kernel_ptr_init() { return (void *)bfs_init_kernel; }
-void *kernel_ptr_layer(bool wide) { return wide ? (void *)bfs_layer_kernel_wide : (void *)bfs_layer_kernel; }
-void *kernel_ptr_finish() { return (void *)bfs_finish_kernel; }
+void *kernel_ptr_layer(bool wide, bool lists)
+{
+    if (wide) return lists ? (void *)bfs_layer_kernel_wide<true> : (void *)bfs_layer_kernel_wide<false>;
+    return lists ? (void *)bfs_layer_kernel<true> : (void *)bfs_layer_kernel<false>;
+}
+void *kernel_ptr_finish(bool lists)
+{
+    return lists ? (void *)bfs_finish_kernel<true> : (void *)bfs_finish_kernel<false>;
+}
 
 int layer_blocks_per_cu(bool wide)
 {
     int occ = 0;
     const hipError_t e =
-        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel_wide, kBlock, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel, kBlock, 0);
+        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel_wide<false>, kBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel<false>, kBlock, 0);
     return e == hipSuccess ? occ : -1;
 }
 

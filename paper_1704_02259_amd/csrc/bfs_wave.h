@@ -98,7 +98,7 @@ static __device__ __forceinline__ int lane_search(int key, int x)
 // done and status itself).  Other kernels set status bits with device-scope
 // atomics, so the flags are read at that scope.
 template <class C_>
-__device__ void record_failure(C_ *C)
+__device__ __forceinline__ void record_failure(C_ *C)
 {
     const int dn = __hip_atomic_load(&C->done, __ATOMIC_RELAXED, AGENT);
     unsigned st = __hip_atomic_load((unsigned *)&C->status, __ATOMIC_RELAXED, AGENT);

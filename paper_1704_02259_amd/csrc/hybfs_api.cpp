@@ -98,6 +98,9 @@ int validate_options(const bfs_options &o)
     if (o.first_writer < 0 || o.first_writer > 1) return set_error(BFS_E_INVALID, "first_writer must be 0 or 1");
     if (o.bu_serial_probes < -1 || o.bu_serial_probes > 1)
         return set_error(BFS_E_INVALID, "bu_serial_probes must be -1, 0 or 1");
+    if (o.td_queue < -1 || o.td_queue > 2) return set_error(BFS_E_INVALID, "td_queue must be -1, 0, 1 or 2");
+    if (o.td_hub_list < -1 || o.td_hub_list > 2)
+        return set_error(BFS_E_INVALID, "td_hub_list must be -1, 0, 1 or 2");
     if (o.graph_launch < 0 || o.graph_launch > 1 || o.profile_layers < 0 || o.profile_layers > 1 ||
         o.async < 0 || o.async > 1 || o.out_on_device < 0 || o.out_on_device > 1)
         return set_error(BFS_E_INVALID, "flag options must be 0 or 1");
@@ -109,6 +112,8 @@ Workspace::~Workspace()
 {
     if (dbuf) hipFree(dbuf);
     if (bin_buf) hipFree(bin_buf);
+    if (q_buf) hipFree(q_buf);
+    if (hq_buf) hipFree(hq_buf);
     if (out_tmp) hipFree(out_tmp);
     if (h_ctrl) hipHostFree(h_ctrl);
     if (h_trace) hipHostFree(h_trace);
@@ -233,6 +238,54 @@ static int ensure_bins(Graph *g, Workspace *w)
     return BFS_OK;
 }
 
+// Library defaults of the queue options (option value 0), from A/B runs on
+// MI355X (harmonic-mean GTEPS, 64 roots at SCALE 20 and 22, 16 at SCALE 26):
+//  * frontier queues lose everywhere: appends to a queue's one tail
+//    serialise (top-down queues: SCALE 20 147 -> 129, SCALE 26 426 -> 418;
+//    every layer: 50 and 264), and a top-down layer's bitmap scan is cheap;
+//  * hub lists written by every step cost more in the big layers than they
+//    save (SCALE 20 101, SCALE 26 427), but the list of layer 0 for layer 1
+//    removes layer 1's scan of the hub table: SCALE 26 426 -> 437, SCALE 22
+//    296 -> 297, SCALE 20 146 -> 143.  So it is on where the table is large
+//    (graphs in the wide build of the layer kernel).
+constexpr int kDefaultQueueMode = QM_OFF;
+
+void queue_modes(const Graph *g, const bfs_options &opt, int *td_queue, int *hub_list)
+{
+    *td_queue = opt.td_queue == 0 ? kDefaultQueueMode : opt.td_queue < 0 ? QM_OFF : opt.td_queue;
+    *hub_list = opt.td_hub_list == 0 ? (g->wide ? HL_LAYER0 : HL_OFF)
+                                     : opt.td_hub_list < 0 ? HL_OFF : opt.td_hub_list;
+}
+
+size_t queue_bytes(const Graph *g, bool queues, bool hub_lists)
+{
+    size_t b = 0;
+    if (queues) b += 2 * align256((size_t)g->n * 4);
+    if (hub_lists) b += 2 * align256((size_t)std::max<long long>(g->n_hub, 1) * sizeof(Item));
+    return b;
+}
+
+// Frontier queues and hub lists, allocated with the first run that uses them.
+static int ensure_queues(Graph *g, Workspace *w, bool queues, bool hub_lists)
+{
+    hipError_t e;
+    if (queues && !w->q_buf) {
+        const size_t a = align256((size_t)g->n * 4);
+        if ((e = hipMalloc(&w->q_buf, 2 * a)) != hipSuccess) return hip_fail(e, "frontier queues");
+        w->q[0] = (int *)w->q_buf;
+        w->q[1] = (int *)((char *)w->q_buf + a);
+    }
+    if (hub_lists && !w->hq_buf) {
+        const long long cap = std::max<long long>(g->n_hub, 1);
+        const size_t a = align256((size_t)cap * sizeof(Item));
+        if ((e = hipMalloc(&w->hq_buf, 2 * a)) != hipSuccess) return hip_fail(e, "hub lists");
+        w->hq[0] = (Item *)w->hq_buf;
+        w->hq[1] = (Item *)((char *)w->hq_buf + a);
+        w->hq_cap = g->n_hub;
+    }
+    return BFS_OK;
+}
+
 // ------------------------------------------------------------------ launch
 void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P)
 {
@@ -275,6 +328,20 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->bin_pairs = w->bin_pairs;
     P->bin_cap = w->bin_pairs ? w->bin_cap : 0;
     P->bin_min_edges = opt.td_binned > 0 ? 1 : (1LL << 22);
+    int qm = QM_OFF, hl = 0;
+    queue_modes(g, opt, &qm, &hl);
+    // without its buffers a mode stays off (the no-allocation entry point)
+    if (!w->q[0]) qm = QM_OFF;
+    if (!w->hq[0]) hl = 0;
+    P->td_queue = qm;
+    P->q0 = w->q[0];
+    P->q1 = w->q[1];
+    P->q_cap = w->q[0] ? g->n : 0;
+    P->hub_list = hl;
+    P->hq0 = w->hq[0];
+    P->hq1 = w->hq[1];
+    P->hq_cap = w->hq_cap;
+    P->q_write = 0;
 }
 
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
@@ -284,6 +351,12 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     const bool bins = g->nbins <= kMaxBins && (opt.td_binned > 0 || (opt.td_binned == 0 && g->bin_auto));
     if (bins) {
         const int rc = ensure_bins(g, w);
+        if (rc) return rc;
+    }
+    if (!w->no_alloc) {
+        int qm = QM_OFF, hl = 0;
+        queue_modes(g, opt, &qm, &hl);
+        const int rc = ensure_queues(g, w, qm != QM_OFF, hl != 0);
         if (rc) return rc;
     }
     Params P;
@@ -344,13 +417,19 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
 int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl,
                             int *par, hipStream_t s, int *layers_enqueued)
 {
+    {
+        int qm = QM_OFF, hl = 0;
+        queue_modes(g, opt, &qm, &hl);
+        const int rc = ensure_queues(g, w, qm != QM_OFF, hl != 0);
+        if (rc) return rc;
+    }
     Params P;
     fill_params(g, w, opt, &P);
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
     char key[160];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k, P.wpg,
-             P.wpg_td, P.hub_deg, P.first_writer, P.serial_probes, grid, L);
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k,
+             P.wpg, P.wpg_td, P.hub_deg, P.first_writer, P.serial_probes, grid, L, P.td_queue, P.hub_list);
     hipError_t e;
     auto it = w->replays.find(key);
     if (it == w->replays.end()) {
@@ -376,7 +455,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         int no_bins = 0;   // the captured sequence has no binned kernels
         for (int i = 0; i < L; ++i) {
             void *args[] = {&R.params, &layer_idx[i], &no_bins};
-            kp.func = kernel_ptr_layer(R.params.wide != 0);
+            kp.func = kernel_ptr_layer(R.params.wide != 0, layer_uses_lists(R.params, i));
             kp.kernelParams = args;
             hipGraphNode_t node;
             if ((e = hipGraphAddKernelNode(&node, R.graph, &prev, 1, &kp)) != hipSuccess)
@@ -384,7 +463,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
             prev = node;
         }
         void *fin_args[] = {&R.params};
-        kp.func = kernel_ptr_finish();
+        kp.func = kernel_ptr_finish(R.params.td_queue != QM_OFF || R.params.hub_list == HL_ALL);
         kp.gridDim = dim3(1);
         kp.blockDim = dim3(kFinishBlock);
         kp.kernelParams = fin_args;

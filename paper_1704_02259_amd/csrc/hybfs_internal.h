@@ -49,11 +49,20 @@ struct Workspace {
     // traversal (the workspace was just cleared, or the last traversal was
     // enqueued in full: its finisher clears them)
     bool counters_zero = true;
+    // the scratch of bfs_run_noalloc: nothing may be allocated for it
+    bool no_alloc = false;
     // binned top-down buckets (allocated on first use)
     void *bin_buf = nullptr;
     int *bin_cnt = nullptr, *bin_off = nullptr, *bin_cur = nullptr;
     unsigned long long *bin_pairs = nullptr;
     long long bin_cap = 0;
+    // frontier queues (2 x n ids) and hub lists (2 x hub-table entries),
+    // allocated with the first run that uses them
+    void *q_buf = nullptr;
+    int *q[2] = {nullptr, nullptr};
+    void *hq_buf = nullptr;
+    Item *hq[2] = {nullptr, nullptr};
+    long long hq_cap = 0;
     // captured launch sequences: key = option set and layer count
     struct Replay {
         hipGraph_t graph = nullptr;
@@ -138,6 +147,10 @@ int validate_options(const bfs_options &o);
 int check_csr(int64_t n, int64_t nnz, const int64_t *off, const int32_t *col, bool need_sorted,
               bool check_symmetry);
 int get_workspace(Graph *g, void *stream, Workspace **out);
+// The queue mode (QM_*) and hub-list flag a run with these options uses.
+void queue_modes(const Graph *g, const bfs_options &opt, int *td_queue, int *hub_list);
+// Device bytes a workspace adds for the frontier queues and hub lists.
+size_t queue_bytes(const Graph *g, bool queues, bool hub_lists);
 // Failures of asynchronous traversals of g on `stream` since the last call
 // (the stream must be synchronized): BFS_E_DEVICE with a message, and the
 // record cleared; BFS_OK when there were none.

@@ -63,6 +63,7 @@ int noalloc_setup(NoAllocDevice &D, hipStream_t s)
     w.ctrl = (Ctrl *)(b + kCtrlOff);
     w.trace = (LayerRec *)(b + kTraceOff);
     w.bytes = kScratchBytes;
+    w.no_alloc = true;   // no frontier queues or hub lists either
     if ((e = hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return hip_fail(e, "clearing the scratch control block");

@@ -40,7 +40,8 @@ class bfs_options(ctypes.Structure):
                 ("async_", ctypes.c_int32), ("profile_layers", ctypes.c_int32),
                 ("graph_launch", ctypes.c_int32), ("td_binned", ctypes.c_int32),
                 ("first_writer", ctypes.c_int32), ("bu_serial_probes", ctypes.c_int32),
-                ("reserved3", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("td_queue", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("td_hub_list", ctypes.c_int32), ("reserved4", ctypes.c_int32)]
 
 
 class bfs_layer_stat(ctypes.Structure):
@@ -89,7 +90,7 @@ class bfs_tune_report(ctypes.Structure):
 
 
 OPTION_KNOBS = ("rule", "alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks", "words_per_wave",
-                "layers_per_launch", "td_binned", "bu_serial_probes")
+                "layers_per_launch", "td_binned", "bu_serial_probes", "td_queue", "td_hub_list")
 
 
 class HybfsError(RuntimeError):
