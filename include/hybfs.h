@@ -197,8 +197,9 @@ typedef struct bfs_options {
                                   frontier bitmap (a list longer than a quarter of
                                   the table is abandoned for the table).  1 = every
                                   step keeps them; 2 = only layer 0 (the root's
-                                  row), for layer 1; -1 = never; 0 (default) = the
-                                  library's choice */
+                                  row), for layer 1; 3 = layer 0 and the top-down
+                                  steps; -1 = never; 0 (default) = the library's
+                                  choice */
     int32_t reserved4;
 } bfs_options;
 

@@ -143,7 +143,7 @@ struct Params {
     long long hq_cap;                    // entries of each (the table's size bounds them)
     int q_write;                         // set per layer: this layer appends its output to
                                          // the next frontier's queue
-    int pad1;
+    int h_write;                         // set per layer: this layer lists the hubs it discovers
 };
 
 __device__ __forceinline__ int *queue_of(const Params &P, int d) { return (d & 1) ? P.q1 : P.q0; }
@@ -153,7 +153,11 @@ __device__ __forceinline__ Item *hubs_of(const Params &P, int d) { return (d & 1
 // hub list whenever the layer before wrote one.
 enum { HL_OFF = 0,
        HL_ALL = 1,                       // every step lists the hubs it discovers
-       HL_LAYER0 = 2 };                  // only layer 0 (the root's row) does, for layer 1
+       HL_LAYER0 = 2,                    // only layer 0 (the root's row) does, for layer 1
+       HL_TD = 3 };                      // layer 0 and the top-down steps do
+
+// Builds of the layer kernel (which lists their code keeps).
+enum { BUILD_PLAIN = 0, BUILD_HUBS = 1, BUILD_QUEUES = 2 };
 
 // Queue modes (Params::td_queue).
 enum { QM_OFF = 0,                       // bitmaps only
@@ -259,8 +263,9 @@ constexpr int kPullWaves = 4;             // wavefronts per block of the batched
 hipError_t launch_init(const Params &p, int grid, hipStream_t s);
 // allow_binned: the three binned kernels follow this layer kernel in the stream
 hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s);
-// whether layer `layer` runs in the build of the layer kernel with queues and hub lists
-bool layer_uses_lists(const Params &p, int layer);
+// the build (BUILD_*) that runs layer `layer`, and the finisher's
+int layer_build(const Params &p, int layer);
+int finish_build(const Params &p);
 hipError_t launch_bin_scan(const Params &p, int layer, hipStream_t s);
 hipError_t launch_bin_scatter(const Params &p, int layer, int grid, hipStream_t s);
 hipError_t launch_bin_reduce(const Params &p, int layer, int grid, hipStream_t s);
@@ -275,8 +280,8 @@ constexpr int kFuseWords = 1024;
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);
 void *kernel_ptr_init();
-void *kernel_ptr_layer(bool wide, bool lists);   // lists: the build with queues and hub lists
-void *kernel_ptr_finish(bool lists);
+void *kernel_ptr_layer(bool wide, int build);
+void *kernel_ptr_finish(int build);
 int layer_blocks_per_cu(bool wide);
 
 }  // namespace hybfs

@@ -305,7 +305,7 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
                 dvq[q] = P.deg[v[q]];
                 mf += (unsigned long long)dvq[q];
                 nh += dvq[q] > P.hub_deg;
-                if (P.hub_list == HL_ALL && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
+                if (P.h_write && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
             }
         }
         if (P.q_write) queue_append4(P, d, win, v);
@@ -333,7 +333,7 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
             dvq[q] = P.deg[v[q]];
             mf += (unsigned long long)dvq[q];
             nh += dvq[q] > P.hub_deg;
-            if (P.hub_list == HL_ALL && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
+            if (P.h_write && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
         }
     }
     if (P.q_write) queue_append4(P, d, win, v);
@@ -678,7 +678,7 @@ __device__ __forceinline__ void bottom_up_step(const Params &P, int d, const uns
                     nf += 1;
                     mf += (unsigned long long)dg[j];
                     nh += dg[j] > P.hub_deg;
-                    if (P.hub_list == HL_ALL && dg[j] > P.hub_deg) hub_stage(hs, (int)v[j]);
+                    if (P.h_write && dg[j] > P.hub_deg) hub_stage(hs, (int)v[j]);
                 }
                 if (lane == wi[j]) tfm = fm;
                 // `next` was cleared one layer ahead: store only nonzero words
@@ -774,12 +774,12 @@ struct LayerView {
     long long q_len, hq_len;         // entries of F_d's queue and hub list
 };
 
-// kLists: the build that keeps frontier queues and hub lists (the options
-// td_queue and td_hub_list) and reads them; the other build has none of
-// their code, so the plain bitmap path pays no registers for them.  With
-// hub lists for layer 1 only, layer 1 runs in the list build and the other
-// layers in the plain one.
-template <bool kLists>
+// kBuild: which lists the build of the layer kernel keeps and reads (BUILD_*):
+// none (the plain bitmap path, which pays no registers for them), hub lists,
+// or frontier queues and hub lists.  The host picks the build per launch
+// (layer_build): with hub lists for layer 1 only, layer 1 runs in the
+// hub-list build and the other layers in the plain one.
+template <int kBuild>
 __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long long gwave, long long nwaves,
                           long long gt, long long nt, bool leader, unsigned long long *s_red,
                           int nwaves_block, LayerView *view, bool same_kernel, int d_hint,
@@ -815,10 +815,8 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
     Params P = Pin;
     P.level = view->level;
     P.parent = view->parent;
-    if (!kLists) {
-        P.td_queue = QM_OFF;
-        P.hub_list = 0;
-    }
+    if (kBuild != BUILD_QUEUES) P.td_queue = QM_OFF;
+    if (kBuild == BUILD_PLAIN) P.hub_list = HL_OFF;
     const LayerState S = view->S;
     const int d = S.d;
     if (d_hint >= 0 && d != d_hint) {
@@ -865,7 +863,7 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
             atomicOr((unsigned *)&C->status, 0x1000u);
         }
     }
-    if (kLists && S.hlist && hub_list_usable(P, view->hq_len)) {
+    if (kBuild != BUILD_PLAIN && S.hlist && hub_list_usable(P, view->hq_len)) {
         src.hubs = hubs_of(P, d);
         src.nhubs = view->hq_len;
         src.hubs_listed = true;
@@ -874,8 +872,9 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
         src.nhubs = view->n_h > 0 ? P.n_hub : 0;
         src.hubs_listed = false;
     }
-    // this layer also writes F_{d+1} as a queue
+    // this layer also writes F_{d+1} as a queue, and lists its hubs
     P.q_write = P.td_queue == QM_ALL || (P.td_queue == QM_TOPDOWN && cur == DIR_TD && !binned);
+    P.h_write = P.hub_list == HL_ALL || (P.hub_list == HL_TD && cur == DIR_TD);
     if (leader) {
         C->bin_layer = binned ? d : -1;
         C->bin_qlen = src.q ? (int)src.qlen : -1;
@@ -903,7 +902,7 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
         Nx.reached_deg = S.reached_deg + m_f;
         // the bottom-up step writes its found vertices into vis itself
         Nx.qform = !P.q_write ? QF_NONE : (cur == DIR_BU ? QF_LIST_VIS : QF_LIST);
-        Nx.hlist = P.hub_list == HL_ALL;     // every step of this layer lists its hubs
+        Nx.hlist = P.h_write;                // this layer lists the hubs it discovers
         C->st[parity ^ 1] = Nx;
         C->parity = parity ^ 1;
         Slot *Z = &C->slot[(d + 2) % kSlots];
@@ -922,7 +921,7 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
     if (binned) bin_count_pass(P, front, hist, src, gwave, nwaves);
     else if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, src, gwave, nwaves, hs);
     else bottom_up_step(P, d, front, next, nf, mf, nh, gwave, nwaves, hs);
-    if (P.hub_list == HL_ALL) hub_flush(P, hs, d, nwaves_block);
+    if (P.h_write) hub_flush(P, hs, d, nwaves_block);
     for (long long w = gt; w < P.W; w += nt) spare[w] = 0ull;   // `next` of layer d+1
     flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, nwaves_block);
     return true;
@@ -1007,7 +1006,7 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
 }
 
 // One layer over the whole grid; the body of both builds of the layer kernel.
-template <bool kLists>
+template <int kBuild>
 __device__ __forceinline__ void layer_grid(const Params &P, int layer, int allow_binned,
                                            unsigned long long *s_red, LayerView *view, unsigned *hist,
                                            HubStage *hs)
@@ -1017,18 +1016,18 @@ __device__ __forceinline__ void layer_grid(const Params &P, int layer, int allow
     const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
-    run_layer<kLists>(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
+    run_layer<kBuild>(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
               kWavesPerBlock, view, false, layer, hist, allow_binned != 0 && P.nbins <= kMaxBins, hs);
 }
 
-template <bool kLists>
+template <int kBuild>
 __global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, int allow_binned)
 {
     __shared__ unsigned long long s_red[3 * kWavesPerBlock];
     __shared__ LayerView view;
     __shared__ unsigned hist[kMaxBins];
     __shared__ HubStage hs;
-    layer_grid<kLists>(P, layer, allow_binned, s_red, &view, hist, &hs);
+    layer_grid<kBuild>(P, layer, allow_binned, s_red, &view, hist, &hs);
 }
 
 // The same kernel built for kWideWavesPerSimd resident wavefronts per SIMD:
@@ -1036,7 +1035,7 @@ __global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, 
 // whose frontier bitmap no longer fits the L2, the layers are chains of
 // dependent probes and row loads, and more chains in flight win; on smaller
 // graphs the spills cost more than the extra wavefronts gain.
-template <bool kLists>
+template <int kBuild>
 __global__ void __launch_bounds__(kBlock, kWideWavesPerSimd) bfs_layer_kernel_wide(Params P, int layer,
                                                                                   int allow_binned)
 {
@@ -1044,11 +1043,11 @@ __global__ void __launch_bounds__(kBlock, kWideWavesPerSimd) bfs_layer_kernel_wi
     __shared__ LayerView view;
     __shared__ unsigned hist[kMaxBins];
     __shared__ HubStage hs;
-    layer_grid<kLists>(P, layer, allow_binned, s_red, &view, hist, &hs);
+    layer_grid<kBuild>(P, layer, allow_binned, s_red, &view, hist, &hs);
 }
 
 // One block runs whatever layers remain, with block barriers between them.
-template <bool kLists>
+template <int kBuild>
 __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
 {
     __shared__ unsigned long long s_red[3 * (kFinishBlock / 64)];
@@ -1061,7 +1060,7 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
         if (threadIdx.x == 0) s_parity = P.ctrl->parity;
         __syncthreads();
         const int parity = s_parity;
-        if (!run_layer<kLists>(P, parity, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, s_red,
+        if (!run_layer<kBuild>(P, parity, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, s_red,
                        kFinishBlock / 64, &view, true, -1, nullptr, false, &hs))
             break;
         __syncthreads();
@@ -1212,6 +1211,8 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
     constexpr int TW = T / 64;
     unsigned long long *next = P.bm + (long long)((d + 1) % 3) * P.W;
     unsigned long long nf = 0, mf = 0, nh = 0;
+    // the layer is top-down: it lists its hubs in both modes that list them there
+    const bool hubs_out = P.hub_list == HL_ALL || P.hub_list == HL_TD;
     for (int tile = blockIdx.x; tile < P.nbins; tile += gridDim.x) {
         const long long v0 = (long long)tile << kBinLog2;
         const long long w0 = v0 >> 6;
@@ -1263,7 +1264,7 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
                     mf += (unsigned long long)dv[q];
                     nh += dv[q] > P.hub_deg;
                 }
-                if (P.hub_list == HL_ALL && found[q] && dv[q] > P.hub_deg) hub_stage(&hs, (int)v[q]);
+                if (hubs_out && found[q] && dv[q] > P.hub_deg) hub_stage(&hs, (int)v[q]);
             }
             if (P.td_queue == QM_ALL) {
                 int vq[4];
@@ -1274,7 +1275,7 @@ __global__ void __launch_bounds__(kReduceBlock) bfs_bin_reduce_kernel(Params P, 
         }
         __syncthreads();
     }
-    if (P.hub_list == HL_ALL) hub_flush(P, &hs, d, kReduceBlock / 64);
+    if (hubs_out) hub_flush(P, &hs, d, kReduceBlock / 64);
     flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, kReduceBlock / 64);
 }
 
@@ -1494,22 +1495,37 @@ hipError_t launch_init(const Params &p, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-bool layer_uses_lists(const Params &p, int layer)
+int layer_build(const Params &p, int layer)
 {
-    return p.td_queue != QM_OFF || p.hub_list == HL_ALL || (p.hub_list == HL_LAYER0 && layer == 1);
+    if (p.td_queue != QM_OFF) return BUILD_QUEUES;
+    if (p.hub_list == HL_ALL || p.hub_list == HL_TD) return BUILD_HUBS;
+    if (p.hub_list == HL_LAYER0 && layer == 1) return BUILD_HUBS;
+    return BUILD_PLAIN;
+}
+
+int finish_build(const Params &p)
+{
+    if (p.td_queue != QM_OFF) return BUILD_QUEUES;
+    if (p.hub_list == HL_ALL || p.hub_list == HL_TD) return BUILD_HUBS;
+    return BUILD_PLAIN;
+}
+
+template <int B>
+static void launch_layer_build(const Params &p, int layer, int allow_binned, int grid, hipStream_t s)
+{
+    if (p.wide)
+        hipLaunchKernelGGL(bfs_layer_kernel_wide<B>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    else
+        hipLaunchKernelGGL(bfs_layer_kernel<B>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
 }
 
 hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s)
 {
-    const bool lists = layer_uses_lists(p, layer);
-    if (p.wide && lists)
-        hipLaunchKernelGGL(bfs_layer_kernel_wide<true>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
-    else if (p.wide)
-        hipLaunchKernelGGL(bfs_layer_kernel_wide<false>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
-    else if (lists)
-        hipLaunchKernelGGL(bfs_layer_kernel<true>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
-    else
-        hipLaunchKernelGGL(bfs_layer_kernel<false>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    switch (layer_build(p, layer)) {
+    case BUILD_QUEUES: launch_layer_build<BUILD_QUEUES>(p, layer, allow_binned, grid, s); break;
+    case BUILD_HUBS: launch_layer_build<BUILD_HUBS>(p, layer, allow_binned, grid, s); break;
+    default: launch_layer_build<BUILD_PLAIN>(p, layer, allow_binned, grid, s); break;
+    }
     return hipGetLastError();
 }
 
@@ -1545,9 +1561,11 @@ hipError_t launch_root(const Params &p, hipStream_t s)
 
 hipError_t launch_finish(const Params &p, hipStream_t s)
 {
-    if (p.td_queue != QM_OFF || p.hub_list == HL_ALL)
-        hipLaunchKernelGGL(bfs_finish_kernel<true>, dim3(1), dim3(kFinishBlock), 0, s, p);
-    else hipLaunchKernelGGL(bfs_finish_kernel<false>, dim3(1), dim3(kFinishBlock), 0, s, p);
+    switch (finish_build(p)) {
+    case BUILD_QUEUES: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_QUEUES>, dim3(1), dim3(kFinishBlock), 0, s, p); break;
+    case BUILD_HUBS: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_HUBS>, dim3(1), dim3(kFinishBlock), 0, s, p); break;
+    default: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_PLAIN>, dim3(1), dim3(kFinishBlock), 0, s, p); break;
+    }
     return hipGetLastError();
 }
 
@@ -1561,22 +1579,29 @@ hipError_t launch_iso_template(const long long *off, long long n, long long W,
 }
 
 void *kernel_ptr_init() { return (void *)bfs_init_kernel; }
-void *kernel_ptr_layer(bool wide, bool lists)
+void *kernel_ptr_layer(bool wide, int build)
 {
-    if (wide) return lists ? (void *)bfs_layer_kernel_wide<true> : (void *)bfs_layer_kernel_wide<false>;
-    return lists ? (void *)bfs_layer_kernel<true> : (void *)bfs_layer_kernel<false>;
+    switch (build) {
+    case BUILD_QUEUES: return wide ? (void *)bfs_layer_kernel_wide<BUILD_QUEUES> : (void *)bfs_layer_kernel<BUILD_QUEUES>;
+    case BUILD_HUBS: return wide ? (void *)bfs_layer_kernel_wide<BUILD_HUBS> : (void *)bfs_layer_kernel<BUILD_HUBS>;
+    default: return wide ? (void *)bfs_layer_kernel_wide<BUILD_PLAIN> : (void *)bfs_layer_kernel<BUILD_PLAIN>;
+    }
 }
-void *kernel_ptr_finish(bool lists)
+void *kernel_ptr_finish(int build)
 {
-    return lists ? (void *)bfs_finish_kernel<true> : (void *)bfs_finish_kernel<false>;
+    switch (build) {
+    case BUILD_QUEUES: return (void *)bfs_finish_kernel<BUILD_QUEUES>;
+    case BUILD_HUBS: return (void *)bfs_finish_kernel<BUILD_HUBS>;
+    default: return (void *)bfs_finish_kernel<BUILD_PLAIN>;
+    }
 }
 
 int layer_blocks_per_cu(bool wide)
 {
     int occ = 0;
     const hipError_t e =
-        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel_wide<false>, kBlock, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel<false>, kBlock, 0);
+        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel_wide<BUILD_PLAIN>, kBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel<BUILD_PLAIN>, kBlock, 0);
     return e == hipSuccess ? occ : -1;
 }
 

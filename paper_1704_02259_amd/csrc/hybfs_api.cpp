@@ -99,8 +99,8 @@ int validate_options(const bfs_options &o)
     if (o.bu_serial_probes < -1 || o.bu_serial_probes > 1)
         return set_error(BFS_E_INVALID, "bu_serial_probes must be -1, 0 or 1");
     if (o.td_queue < -1 || o.td_queue > 2) return set_error(BFS_E_INVALID, "td_queue must be -1, 0, 1 or 2");
-    if (o.td_hub_list < -1 || o.td_hub_list > 2)
-        return set_error(BFS_E_INVALID, "td_hub_list must be -1, 0, 1 or 2");
+    if (o.td_hub_list < -1 || o.td_hub_list > 3)
+        return set_error(BFS_E_INVALID, "td_hub_list must be in [-1, 3]");
     if (o.graph_launch < 0 || o.graph_launch > 1 || o.profile_layers < 0 || o.profile_layers > 1 ||
         o.async < 0 || o.async > 1 || o.out_on_device < 0 || o.out_on_device > 1)
         return set_error(BFS_E_INVALID, "flag options must be 0 or 1");
@@ -342,6 +342,7 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->hq1 = w->hq[1];
     P->hq_cap = w->hq_cap;
     P->q_write = 0;
+    P->h_write = 0;
 }
 
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
@@ -455,7 +456,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         int no_bins = 0;   // the captured sequence has no binned kernels
         for (int i = 0; i < L; ++i) {
             void *args[] = {&R.params, &layer_idx[i], &no_bins};
-            kp.func = kernel_ptr_layer(R.params.wide != 0, layer_uses_lists(R.params, i));
+            kp.func = kernel_ptr_layer(R.params.wide != 0, layer_build(R.params, i));
             kp.kernelParams = args;
             hipGraphNode_t node;
             if ((e = hipGraphAddKernelNode(&node, R.graph, &prev, 1, &kp)) != hipSuccess)
@@ -463,7 +464,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
             prev = node;
         }
         void *fin_args[] = {&R.params};
-        kp.func = kernel_ptr_finish(R.params.td_queue != QM_OFF || R.params.hub_list == HL_ALL);
+        kp.func = kernel_ptr_finish(finish_build(R.params));
         kp.gridDim = dim3(1);
         kp.blockDim = dim3(kFinishBlock);
         kp.kernelParams = fin_args;

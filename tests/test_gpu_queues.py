@@ -10,6 +10,7 @@ equal to the oracle's replay, whatever mode writes and reads the queues:
   td_hub_list=1 the steps that discover vertices above the top-down cut-off
                 list their edge chunks; top-down layers expand hubs from it
   td_hub_list=2 only layer 0 lists them, for layer 1
+  td_hub_list=3 layer 0 and the top-down steps list them
 
 Covered: every direction rule on edge-case graphs and Kronecker SCALE 16 and
 20, the binned top-down step, first-writer parents, each placement of layer 0,
@@ -29,9 +30,10 @@ from tests.test_gpu_single import _check_against_oracle, _gpu_bfs, _small_cases
 
 pytestmark = pytest.mark.gpu
 
-MODES = [dict(td_queue=1), dict(td_queue=2), dict(td_hub_list=1), dict(td_hub_list=2),
-         dict(td_queue=1, td_hub_list=1), dict(td_queue=2, td_hub_list=1), dict(td_queue=1, td_hub_list=2)]
-MODE_IDS = ["q1", "q2", "hubs", "hubs0", "q1+hubs", "q2+hubs", "q1+hubs0"]
+MODES = [dict(td_queue=1), dict(td_queue=2), dict(td_hub_list=1), dict(td_hub_list=2), dict(td_hub_list=3),
+         dict(td_queue=1, td_hub_list=1), dict(td_queue=2, td_hub_list=1), dict(td_queue=1, td_hub_list=2),
+         dict(td_queue=2, td_hub_list=3)]
+MODE_IDS = ["q1", "q2", "hubs", "hubs0", "hubsTD", "q1+hubs", "q2+hubs", "q1+hubs0", "q2+hubsTD"]
 
 
 def _say(*a):
