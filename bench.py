@@ -130,7 +130,7 @@ def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
     troots = inputs.pick_roots(g, k, inputs.ROOT_SEED[int(workload[4:])] + 500)
     sopt, _ = G.autotune(troots[:16], mode="single", max_trials=24, stream=sp)
     skw = {kk: vv for kk, vv in sopt.items() if kk in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
-                                                       "words_per_wave", "bu_serial_probes")}
+                                                       "words_per_wave", "bu_serial_probes", "alpha_binned")}
     # single-root runs (warm-up pass adapts the launch depth), then timed
     te = []
     for i, r in enumerate(roots):
@@ -486,7 +486,7 @@ def single_root_leg(torch, hybfs, dev, workload, args, nroots, cpu_budget_s, bal
         t0 = time.time()
         topt, trep = G.autotune(troots, mode="single", max_trials=args.tune_trials, stream=sp)
         kw = {k: v for k, v in topt.items() if k in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
-                                                       "words_per_wave", "bu_serial_probes")}
+                                                       "words_per_wave", "bu_serial_probes", "alpha_binned")}
         tuning = {"options": kw, "trials": trep["trials"], "tune_roots": len(troots),
                   "speedup_on_tune_roots": round(trep["start_us"] / trep["best_us"], 3)}
         log(f"autotune {time.time() - t0:.1f}s: {tuning}")

@@ -200,7 +200,30 @@ typedef struct bfs_options {
                                   row), for layer 1; 3 = layer 0 and the top-down
                                   steps; -1 = never; 0 (default) = the library's
                                   choice */
-    int32_t reserved4;
+    int32_t alpha_binned;      /* edge rule for a layer whose top-down step would run
+                                  binned (td_binned): stay top-down while
+                                  m_f * alpha_binned <= m_u, even where alpha says
+                                  bottom-up.  The binned step streams its edges
+                                  instead of issuing a random atomic per edge, so
+                                  its switch point is its own (Algorithm 3's f is
+                                  architecture specific).  0 (default) = the
+                                  library's choice (alpha where no layer bins) */
+    int32_t bu_filter;         /* membership filter of small frontiers: a top-down
+                                  layer of at most 2^16 frontier edges sets two
+                                  hashed bits per discovered vertex in a 2^17-bit
+                                  filter, and a following bottom-up layer of at most
+                                  2^16 frontier vertices loads it into LDS and tests
+                                  it before each frontier-bit probe (most probes of
+                                  such a layer miss, and the filter answers them
+                                  without the frontier bitmap).  Only on graphs that
+                                  run the wide build of the layer kernel (2^24
+                                  vertices and more).  1 = on, -1 = off, 0 (default)
+                                  = the library's choice */
+    int32_t count_work;        /* 1: count each layer's work on the device and report
+                                  it in stats->layers[i].work (synchronous runs with
+                                  stats only).  The layers then run in a build of the
+                                  layer kernel that counts (slower; frontier queues
+                                  off); results are unchanged.  0 (default): no counts */
 } bfs_options;
 
 /* Fill defaults: edge rule, alpha 14, beta 24, probe_k 8, td_hub_degree 256,
@@ -220,6 +243,15 @@ typedef struct bfs_layer_stat {
                            only, else 0); layers past the enqueued kernels,
                            run by the finisher, report 0 */
     double  kernel_us;  /* HIP-event duration of this layer's kernel (profile_layers), else 0 */
+    int64_t work[6];    /* count_work runs only, else 0.  Bottom-up layer: vertices
+                           examined, phase-1 frontier probes (the first probe_k
+                           positions of each row, Algorithms 4-5), rows continued in
+                           phase 2 (the wavefront-cooperative scan of Algorithm 2),
+                           phase-2 wavefront steps of 64 entries, phase-2 entries
+                           probed, vertices found.  Top-down layer (Algorithm 1):
+                           edges examined, candidate targets (in no finished layer),
+                           atomic updates issued, vertices discovered, 0, 0.  A
+                           binned top-down layer reports 0 */
 } bfs_layer_stat;
 
 typedef struct bfs_stats {
@@ -453,7 +485,8 @@ int bfs_graph_sync(bfs_graph_t g, void *stream);
  *     must be 0;
  *   - the binned top-down step is not used (its buckets would need an
  *     allocation; results do not depend on it);
- *   - stats->device_us and the per-layer times are 0 (no events).
+ *   - stats->device_us, the per-layer times and work counts are 0 (no
+ *     events, no count_work).
  * The graph must live on the current device.  All calls on one device share
  * its array, which keeps the last call's contents; the library runs them one
  * at a time (a lock per device), so concurrent calls from several threads

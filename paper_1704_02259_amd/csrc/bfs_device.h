@@ -9,7 +9,8 @@ namespace hybfs {
 constexpr int kBlock = 256;                    // threads per block of the layer kernels
 constexpr int kWave = 64;                      // CDNA wavefront
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kFinishBlock = 1024;             // single-block finisher
+constexpr int kFinishBlock = 1024;             // one-block kernels
+constexpr int kFinisherBlock = 512;            // the traversal's finisher
 constexpr int kSlots = 4;                      // ring of per-layer counter slots
 
 enum { DIR_TD = 0, DIR_BU = 1 };
@@ -46,7 +47,9 @@ struct LayerState {
     long long reached_deg;           // their degree sum
     int qform;                       // QF_*: F_d's queue, written by the layer before
     int hlist;                       // 1: F_d's hub list was written (complete unless too long)
-    long long pad[2];
+    int filt;                        // 1: F_d's membership filter was written
+    int pad1;
+    long long pad[1];
 };
 
 // Trace of one processed layer, written by block 0.
@@ -113,6 +116,7 @@ struct Params {
     int root;
     int rule;
     long long alpha, beta;
+    long long alpha_bin;                 // edge rule's alpha for a layer that would run binned
     int async_run;                       // enqueued asynchronously (failures kept for bfs_graph_sync)
     int first_writer;                    // top-down parents by first writer, not minimum
     // binned top-down (large top-down layers): frontier edges are bucketed by
@@ -144,6 +148,16 @@ struct Params {
     int q_write;                         // set per layer: this layer appends its output to
                                          // the next frontier's queue
     int h_write;                         // set per layer: this layer lists the hubs it discovers
+    // membership filters of small frontiers: 2^kFilterLog2 bits (two hashed
+    // bits per member), three rotating like the bitmaps; a bottom-up layer
+    // whose frontier has one tests it in LDS before each frontier-bit probe
+    unsigned *filt;
+    int f_write;                         // set per layer: this layer fills the next frontier's filter
+    int use_filter;                      // filters are kept and used
+    // per-layer work counters (statistics build only): kCounts per layer
+    unsigned long long *pstat;
+    int count;                           // 1: count (the statistics build runs the layers)
+    int pad3;
 };
 
 __device__ __forceinline__ int *queue_of(const Params &P, int d) { return (d & 1) ? P.q1 : P.q0; }
@@ -156,8 +170,19 @@ enum { HL_OFF = 0,
        HL_LAYER0 = 2,                    // only layer 0 (the root's row) does, for layer 1
        HL_TD = 3 };                      // layer 0 and the top-down steps do
 
-// Builds of the layer kernel (which lists their code keeps).
-enum { BUILD_PLAIN = 0, BUILD_HUBS = 1, BUILD_QUEUES = 2 };
+// Builds of the layer kernel (which lists their code keeps; the last one
+// counts the work of each layer instead).
+enum { BUILD_PLAIN = 0, BUILD_HUBS = 1, BUILD_QUEUES = 2, BUILD_COUNTS = 3 };
+
+// Work counters of one layer (statistics build).  Bottom-up: vertices
+// examined, phase-1 frontier probes, rows continued in phase 2, phase-2
+// wavefront steps, phase-2 entries probed, vertices found.  Top-down: edges
+// examined, candidates (target in no finished layer), atomic minima issued,
+// vertices discovered, and two unused.
+constexpr int kCounts = 6;
+struct WorkCount {
+    unsigned long long c[kCounts];
+};
 
 // Queue modes (Params::td_queue).
 enum { QM_OFF = 0,                       // bitmaps only
@@ -168,8 +193,15 @@ enum { QM_OFF = 0,                       // bitmaps only
                                          // (bottom-up and binned steps convert their output
                                          // bitmap words), every top-down layer reads one
 
+constexpr int kFilterLog2 = 17;                // 16 KiB of filter bits, the size of the LDS tile histogram
+constexpr int kFilterWords = (1 << kFilterLog2) / 32;
+// a top-down layer of at most this many frontier edges fills the filter of its
+// output, and a bottom-up layer of at most this many frontier vertices uses it
+constexpr long long kFilterMaxEdges = 1 << 16;
+constexpr long long kFilterMaxFrontier = 1 << 16;
 constexpr int kBinLog2 = 14;                   // destination tile: 16384 vertices, 64 KiB of minima in LDS
 constexpr int kMaxBins = 4096;
+static_assert(kFilterWords <= kMaxBins, "the LDS filter shares the tile histogram's space");
 constexpr int kWideWavesPerSimd = 6;           // residency the wide layer kernel is built for
 
 // ---------------------------------------------------------------------------
@@ -280,7 +312,9 @@ constexpr int kFuseWords = 1024;
 hipError_t launch_iso_template(const long long *off, long long n, long long W,
                                unsigned long long *iso, hipStream_t s);
 void *kernel_ptr_init();
-void *kernel_ptr_layer(bool wide, int build);
+void *kernel_ptr_layer(bool wide, int build, bool filter);
+// whether layer `layer` runs in the wide build with the small-frontier filters
+bool layer_filter(const Params &p, int layer);
 void *kernel_ptr_finish(int build);
 int layer_blocks_per_cu(bool wide);
 

@@ -246,6 +246,34 @@ __device__ __forceinline__ void hub_flush(const Params &P, HubStage *hs, int d, 
 }
 
 // ---------------------------------------------------------------------------
+// Membership filter of a small frontier (a Bloom filter with two hashes over
+// 2^kFilterLog2 bits).  A bottom-up layer after a small top-down layer probes
+// mostly non-members: the filter, copied into LDS, answers most of them
+// without touching the frontier bitmap, which at 2^26 vertices does not fit
+// in the L2.  Members always pass; a pass is confirmed with the bitmap.
+__device__ __forceinline__ unsigned filt_h1(int v) { return (unsigned)v & ((1u << kFilterLog2) - 1u); }
+__device__ __forceinline__ unsigned filt_h2(int v) { return ((unsigned)v * 2654435761u) >> (32 - kFilterLog2); }
+
+__device__ __forceinline__ unsigned *filt_of(const Params &P, int d) { return P.filt + (d % 3) * kFilterWords; }
+
+__device__ __forceinline__ void filter_set(unsigned *f, int v)
+{
+    const unsigned a = filt_h1(v), b = filt_h2(v);
+    atomicOr(&f[a >> 5], 1u << (a & 31));
+    atomicOr(&f[b >> 5], 1u << (b & 31));
+}
+
+// Frontier test of a bottom-up probe: the LDS filter first when there is one.
+__device__ __forceinline__ bool probe_front(const unsigned long long *front, const unsigned *lf, int u)
+{
+    if (lf) {
+        const unsigned a = filt_h1(u), b = filt_h2(u);
+        if (!((lf[a >> 5] >> (a & 31)) & (lf[b >> 5] >> (b & 31)) & 1u)) return false;
+    }
+    return test_bit(front, u);
+}
+
+// ---------------------------------------------------------------------------
 // Up to four frontier edges (u_q -> col[j_q]) per lane of a top-down layer.
 // A target v is a candidate when it is in no layer <= d (neither in vis nor
 // in the frontier).  Canonical parent = the minimum frontier neighbour: a plain
@@ -256,7 +284,7 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
                                           const long long (&jq)[4], const bool (&okq)[4],
                                           const unsigned long long *front, unsigned long long *next,
                                           unsigned long long &nf, unsigned long long &mf,
-                                          unsigned long long &nh, HubStage *hs)
+                                          unsigned long long &nh, HubStage *hs, WorkCount &wc)
 {
     int v[4];
 #pragma unroll
@@ -277,6 +305,10 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
             const int w = v[q] >> 6;
             cand[q] = !(((P.vis[w] | front[w]) >> (v[q] & 63)) & 1ull);
         }
+        if (P.count) {
+            wc.c[0] += v[q] >= 0;
+            wc.c[1] += cand[q];
+        }
     }
     if (P.first_writer) {
         // the edge whose atomic OR sets v's next-frontier bit discovers v and
@@ -291,6 +323,7 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
             const unsigned long long bit = 1ull << (v[q] & 63);
             cand[q] = cand[q] && !(nw[q] & bit);
             ob[q] = cand[q] ? atomicOr(&next[v[q] >> 6], bit) : 0ull;
+            if (P.count) wc.c[2] += cand[q];
         }
         bool win[4];
         int dvq[4];
@@ -306,6 +339,8 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
                 mf += (unsigned long long)dvq[q];
                 nh += dvq[q] > P.hub_deg;
                 if (P.h_write && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
+                if (P.f_write) filter_set(filt_of(P, d + 1), v[q]);
+                if (P.count) wc.c[3] += 1;
             }
         }
         if (P.q_write) queue_append4(P, d, win, v);
@@ -319,6 +354,7 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
     for (int q = 0; q < 4; ++q) {
         cand[q] = cand[q] && (unsigned)uq[q] < pv[q];
         old[q] = cand[q] ? atomicMin((unsigned int *)&P.parent[v[q]], (unsigned int)uq[q]) : 0u;
+        if (P.count) wc.c[2] += cand[q];
     }
     bool win[4];
     int dvq[4];
@@ -334,6 +370,8 @@ __device__ __forceinline__ void td_edges4(const Params &P, int d, const int (&uq
             mf += (unsigned long long)dvq[q];
             nh += dvq[q] > P.hub_deg;
             if (P.h_write && dvq[q] > P.hub_deg) hub_stage(hs, v[q]);
+            if (P.f_write) filter_set(filt_of(P, d + 1), v[q]);
+            if (P.count) wc.c[3] += 1;
         }
     }
     if (P.q_write) queue_append4(P, d, win, v);
@@ -500,10 +538,10 @@ __device__ __forceinline__ void td_scan(const Params &P, const unsigned long lon
 __device__ __forceinline__ void top_down_step(const Params &P, int d, const unsigned long long *front,
                               unsigned long long *next, unsigned long long &nf,
                               unsigned long long &mf, unsigned long long &nh, const FrontSrc &src,
-                              long long gwave, long long nwaves, HubStage *hs)
+                              long long gwave, long long nwaves, HubStage *hs, WorkCount &wc)
 {
     auto sink = [&](const int (&uq)[4], const long long (&jq)[4], const bool (&okq)[4]) {
-        td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh, hs);
+        td_edges4(P, d, uq, jq, okq, front, next, nf, mf, nh, hs, wc);
     };
     td_scan(P, front, src, true, gwave, nwaves, sink);
 }
@@ -522,8 +560,8 @@ __device__ __forceinline__ void top_down_step(const Params &P, int d, const unsi
 //            first hit is taken with ballot + find-first-set.
 // The first hit in ascending order is the canonical parent.
 __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned long long *front,
-                                                 long long v, bool act, int dg, int KS, int K,
-                                                 bool &found, int &par)
+                                                 const unsigned *lf, long long v, bool act, int dg, int KS,
+                                                 int K, bool &found, int &par, WorkCount &wc)
 {
     const int lane = __lane_id();
     // phase 1b: positions KS..K-1 from the column array
@@ -544,15 +582,18 @@ __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned
         }
         bool h0 = false, h1 = false, h2 = false, h3 = false;
         if (P.serial_probes) {
-            h0 = c0 >= 0 && test_bit(front, c0);
-            h1 = !h0 && c1 >= 0 && test_bit(front, c1);
-            h2 = !h0 && !h1 && c2 >= 0 && test_bit(front, c2);
-            h3 = !h0 && !h1 && !h2 && c3 >= 0 && test_bit(front, c3);
+            h0 = c0 >= 0 && probe_front(front, lf, c0);
+            h1 = !h0 && c1 >= 0 && probe_front(front, lf, c1);
+            h2 = !h0 && !h1 && c2 >= 0 && probe_front(front, lf, c2);
+            h3 = !h0 && !h1 && !h2 && c3 >= 0 && probe_front(front, lf, c3);
+            if (P.count)
+                wc.c[1] += (c0 >= 0) + (!h0 && c1 >= 0) + (!h0 && !h1 && c2 >= 0) + (!h0 && !h1 && !h2 && c3 >= 0);
         } else {
-            if (c0 >= 0) h0 = test_bit(front, c0);
-            if (c1 >= 0) h1 = test_bit(front, c1);
-            if (c2 >= 0) h2 = test_bit(front, c2);
-            if (c3 >= 0) h3 = test_bit(front, c3);
+            if (P.count) wc.c[1] += (c0 >= 0) + (c1 >= 0) + (c2 >= 0) + (c3 >= 0);
+            if (c0 >= 0) h0 = probe_front(front, lf, c0);
+            if (c1 >= 0) h1 = probe_front(front, lf, c1);
+            if (c2 >= 0) h2 = probe_front(front, lf, c2);
+            if (c3 >= 0) h3 = probe_front(front, lf, c3);
         }
         if (live) {
             if (h0) { found = true; par = c0; }
@@ -565,6 +606,7 @@ __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned
     // phase 2: the rest of each unresolved row, one row at a time
     const int KP = max(K, KS);
     unsigned long long rem = __ballot(need_s && !found && dg > KP);
+    if (P.count && lane == 0) wc.c[2] += __popcll(rem);
     while (rem) {
         const int k = __ffsll((long long)rem) - 1;
         rem &= rem - 1;
@@ -577,7 +619,11 @@ __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned
             bool hit = false;
             if (j < ek) {
                 u = P.col[j];
-                hit = test_bit(front, u);
+                hit = probe_front(front, lf, u);
+            }
+            if (P.count) {
+                wc.c[3] += lane == 0;
+                wc.c[4] += j < ek;
             }
             const unsigned long long hb = __ballot(hit);
             if (hb) {
@@ -595,7 +641,7 @@ __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned
 __device__ __forceinline__ void bottom_up_step(const Params &P, int d, const unsigned long long *front,
                                unsigned long long *next, unsigned long long &nf,
                                unsigned long long &mf, unsigned long long &nh, long long gwave,
-                               long long nwaves, HubStage *hs)
+                               long long nwaves, HubStage *hs, const unsigned *lf, WorkCount &wc)
 {
     const int lane = __lane_id();
     const int K = P.probe_k;
@@ -647,19 +693,25 @@ __device__ __forceinline__ void bottom_up_step(const Params &P, int d, const uns
             for (int j = 0; j < 2; ++j) {
                 found[j] = false;
                 par[j] = -1;
+                if (P.count) wc.c[0] += act[j];
                 if (P.serial_probes) {
                     // one frontier-bit probe at a time, none after the first hit
 #pragma unroll
-                    for (int p = 0; p < 4; ++p)
-                        if (!found[j] && c[j][p] >= 0 && test_bit(front, c[j][p])) {
+                    for (int p = 0; p < 4; ++p) {
+                        if (P.count) wc.c[1] += !found[j] && c[j][p] >= 0;
+                        if (!found[j] && c[j][p] >= 0 && probe_front(front, lf, c[j][p])) {
                             found[j] = true;
                             par[j] = c[j][p];
                         }
+                    }
                     continue;
                 }
                 bool h[4];
 #pragma unroll
-                for (int p = 0; p < 4; ++p) h[p] = c[j][p] >= 0 && test_bit(front, c[j][p]);
+                for (int p = 0; p < 4; ++p) {
+                    h[p] = c[j][p] >= 0 && probe_front(front, lf, c[j][p]);
+                    if (P.count) wc.c[1] += c[j][p] >= 0;
+                }
 #pragma unroll
                 for (int p = 3; p >= 0; --p)
                     if (h[p]) {
@@ -670,8 +722,9 @@ __device__ __forceinline__ void bottom_up_step(const Params &P, int d, const uns
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (wi[j] < 0) continue;
-                bu_finish_vertex(P, front, v[j], act[j], dg[j], KS, K, found[j], par[j]);
+                bu_finish_vertex(P, front, lf, v[j], act[j], dg[j], KS, K, found[j], par[j], wc);
                 const unsigned long long fm = __ballot(found[j]);
+                if (P.count) wc.c[5] += found[j];
                 if (found[j]) {
                     P.level[v[j]] = d + 1;
                     P.parent[v[j]] = par[j];
@@ -779,7 +832,9 @@ struct LayerView {
 // or frontier queues and hub lists.  The host picks the build per launch
 // (layer_build): with hub lists for layer 1 only, layer 1 runs in the
 // hub-list build and the other layers in the plain one.
-template <int kBuild>
+// kFilter: the build keeps the membership filters of small frontiers (only the
+// wide build, used where the frontier bitmap does not fit in the L2).
+template <int kBuild, bool kFilter>
 __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long long gwave, long long nwaves,
                           long long gt, long long nt, bool leader, unsigned long long *s_red,
                           int nwaves_block, LayerView *view, bool same_kernel, int d_hint,
@@ -787,7 +842,7 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
 {
     Ctrl *C = Pin.ctrl;
     if (threadIdx.x == 0) {
-        hub_stage_reset(hs);
+        if (kBuild != BUILD_PLAIN) hub_stage_reset(hs);
         view->done = C->done;
         view->level = C->level;
         view->parent = C->parent;
@@ -806,8 +861,13 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
         view->n_f = a;
         view->m_f = b;
         view->n_h = c;
-        view->q_len = (long long)(same_kernel ? ld_relaxed(&sl.c[0][kQueueTail]) : sl.c[0][kQueueTail]);
-        view->hq_len = (long long)(same_kernel ? ld_relaxed(&sl.c[0][kHubTail]) : sl.c[0][kHubTail]);
+        // list lengths only where the build reads lists
+        view->q_len = kBuild != BUILD_QUEUES ? 0
+                                             : (long long)(same_kernel ? ld_relaxed(&sl.c[0][kQueueTail])
+                                                                       : sl.c[0][kQueueTail]);
+        view->hq_len = kBuild == BUILD_PLAIN ? 0
+                                             : (long long)(same_kernel ? ld_relaxed(&sl.c[0][kHubTail])
+                                                                       : sl.c[0][kHubTail]);
     }
     __syncthreads();
     if (view->done) return false;
@@ -817,6 +877,8 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
     P.parent = view->parent;
     if (kBuild != BUILD_QUEUES) P.td_queue = QM_OFF;
     if (kBuild == BUILD_PLAIN) P.hub_list = HL_OFF;
+    if (kBuild != BUILD_COUNTS) P.count = 0;
+    if (!kFilter) P.use_filter = 0;
     const LayerState S = view->S;
     const int d = S.d;
     if (d_hint >= 0 && d != d_hint) {
@@ -843,10 +905,16 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
         }
         return false;
     }
-    const int cur = decide(P, S.dir_prev, n_f, m_f, m_u, v_u);
+    int cur = decide(P, S.dir_prev, n_f, m_f, m_u, v_u);
+    // a layer that can run binned keeps top-down by its own alpha: the binned
+    // step streams its edges through buckets instead of a random atomic per
+    // edge, so it stays cheaper than a bottom-up scan for longer
+    const bool can_bin = allow_binned && m_f >= P.bin_min_edges && m_f <= P.bin_cap;
+    if (cur == DIR_BU && S.dir_prev == DIR_TD && P.rule == RULE_EDGES && can_bin && m_f * P.alpha_bin <= m_u)
+        cur = DIR_TD;
     // a large top-down layer is bucketed by destination tile when the three
     // binned kernels follow this one (every block decides the same)
-    const bool binned = allow_binned && cur == DIR_TD && m_f >= P.bin_min_edges && m_f <= P.bin_cap;
+    const bool binned = can_bin && cur == DIR_TD;
     // where a top-down step finds F_d and its hubs
     FrontSrc src;
     src.q = nullptr;
@@ -875,6 +943,11 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
     // this layer also writes F_{d+1} as a queue, and lists its hubs
     P.q_write = P.td_queue == QM_ALL || (P.td_queue == QM_TOPDOWN && cur == DIR_TD && !binned);
     P.h_write = P.hub_list == HL_ALL || (P.hub_list == HL_TD && cur == DIR_TD);
+    // a small top-down layer fills its output's membership filter, which a
+    // bottom-up layer with a small frontier uses (in the LDS of the tile
+    // histogram, so not in the finisher, which has none)
+    P.f_write = P.use_filter && cur == DIR_TD && !binned && m_f <= kFilterMaxEdges;
+    const bool use_filter = kFilter && cur == DIR_BU && S.filt && n_f <= kFilterMaxFrontier && hist != nullptr;
     if (leader) {
         C->bin_layer = binned ? d : -1;
         C->bin_qlen = src.q ? (int)src.qlen : -1;
@@ -903,6 +976,7 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
         // the bottom-up step writes its found vertices into vis itself
         Nx.qform = !P.q_write ? QF_NONE : (cur == DIR_BU ? QF_LIST_VIS : QF_LIST);
         Nx.hlist = P.h_write;                // this layer lists the hubs it discovers
+        Nx.filt = P.f_write;
         C->st[parity ^ 1] = Nx;
         C->parity = parity ^ 1;
         Slot *Z = &C->slot[(d + 2) % kSlots];
@@ -918,9 +992,26 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
     unsigned long long *next = P.bm + (long long)((d + 1) % 3) * P.W;
     unsigned long long *spare = P.bm + (long long)((d + 2) % 3) * P.W;
     unsigned long long nf = 0, mf = 0, nh = 0;
+    if (P.use_filter)
+        for (long long w = gt; w < kFilterWords; w += nt) filt_of(P, d + 2)[w] = 0u;   // F_{d+2}'s filter
+    if (use_filter) {
+        const unsigned *gf = filt_of(P, d);
+        for (int i = threadIdx.x; i < kFilterWords; i += nwaves_block * 64) hist[i] = gf[i];
+        __syncthreads();
+    }
+    WorkCount wc;
+#pragma unroll
+    for (int k = 0; k < kCounts; ++k) wc.c[k] = 0;
     if (binned) bin_count_pass(P, front, hist, src, gwave, nwaves);
-    else if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, src, gwave, nwaves, hs);
-    else bottom_up_step(P, d, front, next, nf, mf, nh, gwave, nwaves, hs);
+    else if (cur == DIR_TD) top_down_step(P, d, front, next, nf, mf, nh, src, gwave, nwaves, hs, wc);
+    else bottom_up_step(P, d, front, next, nf, mf, nh, gwave, nwaves, hs, use_filter ? hist : nullptr, wc);
+    if (P.count && d < P.trace_cap) {
+#pragma unroll
+        for (int k = 0; k < kCounts; ++k) {
+            const unsigned long long t = wave_sum_u64(wc.c[k]);
+            if (__lane_id() == 0 && t) atomicAdd(&P.pstat[(long long)d * kCounts + k], t);
+        }
+    }
     if (P.h_write) hub_flush(P, hs, d, nwaves_block);
     for (long long w = gt; w < P.W; w += nt) spare[w] = 0ull;   // `next` of layer d+1
     flush_counters(nf, mf, nh, &C->slot[(d + 1) % kSlots], s_red, nwaves_block);
@@ -967,6 +1058,10 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
     long long root_chunks = root_hub ? (deg_r + (1ll << P.chunk_log2) - 1) >> P.chunk_log2 : 0;
     if (root_chunks > hub_list_limit(P)) root_chunks = -1;   // too long: layer 0 scans the table
     for (long long c = gt; c < root_chunks; c += nt) hubs_of(P, 0)[c] = Item{root, (int)c};   // F_0's hub list
+    if (P.use_filter)
+        for (long long w = gt; w < 3 * kFilterWords; w += nt) P.filt[w] = 0u;              // no filters yet
+    if (P.count)
+        for (long long i = gt; i < (long long)P.trace_cap * kCounts; i += nt) P.pstat[i] = 0ull;
     if (gt == 0) {
         Ctrl *C = P.ctrl;
         C->async_run = P.async_run;
@@ -988,7 +1083,9 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
         S.reached_deg = 0;
         S.qform = P.td_queue != QM_OFF ? QF_LIST : QF_NONE;
         S.hlist = P.hub_list != HL_OFF && root_chunks >= 0;
-        S.pad[0] = S.pad[1] = 0;
+        S.filt = 0;
+        S.pad1 = 0;
+        S.pad[0] = 0;
         C->st[0] = S;
         C->st[1] = S;
         C->status = 0;
@@ -1006,7 +1103,7 @@ __global__ void __launch_bounds__(kBlock) bfs_init_kernel(Params P)
 }
 
 // One layer over the whole grid; the body of both builds of the layer kernel.
-template <int kBuild>
+template <int kBuild, bool kFilter>
 __device__ __forceinline__ void layer_grid(const Params &P, int layer, int allow_binned,
                                            unsigned long long *s_red, LayerView *view, unsigned *hist,
                                            HubStage *hs)
@@ -1016,7 +1113,7 @@ __device__ __forceinline__ void layer_grid(const Params &P, int layer, int allow
     const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
-    run_layer<kBuild>(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
+    run_layer<kBuild, kFilter>(P, parity, gwave, nwaves, gt, nt, blockIdx.x == 0 && threadIdx.x == 0, s_red,
               kWavesPerBlock, view, false, layer, hist, allow_binned != 0 && P.nbins <= kMaxBins, hs);
 }
 
@@ -1027,7 +1124,7 @@ __global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, 
     __shared__ LayerView view;
     __shared__ unsigned hist[kMaxBins];
     __shared__ HubStage hs;
-    layer_grid<kBuild>(P, layer, allow_binned, s_red, &view, hist, &hs);
+    layer_grid<kBuild, false>(P, layer, allow_binned, s_red, &view, hist, &hs);
 }
 
 // The same kernel built for kWideWavesPerSimd resident wavefronts per SIMD:
@@ -1035,7 +1132,7 @@ __global__ void __launch_bounds__(kBlock) bfs_layer_kernel(Params P, int layer, 
 // whose frontier bitmap no longer fits the L2, the layers are chains of
 // dependent probes and row loads, and more chains in flight win; on smaller
 // graphs the spills cost more than the extra wavefronts gain.
-template <int kBuild>
+template <int kBuild, bool kFilter>
 __global__ void __launch_bounds__(kBlock, kWideWavesPerSimd) bfs_layer_kernel_wide(Params P, int layer,
                                                                                   int allow_binned)
 {
@@ -1043,25 +1140,29 @@ __global__ void __launch_bounds__(kBlock, kWideWavesPerSimd) bfs_layer_kernel_wi
     __shared__ LayerView view;
     __shared__ unsigned hist[kMaxBins];
     __shared__ HubStage hs;
-    layer_grid<kBuild>(P, layer, allow_binned, s_red, &view, hist, &hs);
+    layer_grid<kBuild, kFilter>(P, layer, allow_binned, s_red, &view, hist, &hs);
 }
 
 // One block runs whatever layers remain, with block barriers between them.
+// One block of kFinisherBlock threads: half the size of the other one-block
+// kernels, so that run_layer fits in its registers without spilling (a
+// kernel with spills pays for private-memory setup at every launch, and the
+// finisher runs after every traversal).
 template <int kBuild>
-__global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
+__global__ void __launch_bounds__(kFinisherBlock) bfs_finish_kernel(Params P)
 {
-    __shared__ unsigned long long s_red[3 * (kFinishBlock / 64)];
+    __shared__ unsigned long long s_red[3 * (kFinisherBlock / 64)];
     __shared__ int s_parity;
     __shared__ LayerView view;
     __shared__ HubStage hs;
     const long long gwave = threadIdx.x >> 6;
-    const long long nwaves = kFinishBlock / 64;
+    const long long nwaves = kFinisherBlock / 64;
     for (;;) {
         if (threadIdx.x == 0) s_parity = P.ctrl->parity;
         __syncthreads();
         const int parity = s_parity;
-        if (!run_layer<kBuild>(P, parity, gwave, nwaves, threadIdx.x, kFinishBlock, threadIdx.x == 0, s_red,
-                       kFinishBlock / 64, &view, true, -1, nullptr, false, &hs))
+        if (!run_layer<kBuild, false>(P, parity, gwave, nwaves, threadIdx.x, kFinisherBlock, threadIdx.x == 0,
+                                      s_red, kFinisherBlock / 64, &view, true, -1, nullptr, false, &hs))
             break;
         __syncthreads();
     }
@@ -1070,7 +1171,7 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_finish_kernel(Params P)
     __syncthreads();
     unsigned long long *c = &P.ctrl->slot[0].c[0][0];
     constexpr int kCounters = (int)(sizeof(Slot) / sizeof(unsigned long long)) * kSlots;
-    for (int i = threadIdx.x; i < kCounters; i += kFinishBlock) c[i] = 0ull;
+    for (int i = threadIdx.x; i < kCounters; i += kFinisherBlock) c[i] = 0ull;
     if (threadIdx.x == 0) record_failure(P.ctrl);
 }
 
@@ -1312,6 +1413,7 @@ __device__ void layer0_state(const Params &P, Ctrl *C, const LayerState &S, long
     Nx.reached_deg = deg_r;
     Nx.qform = P.td_queue != QM_OFF ? QF_LIST : QF_NONE;   // F_1 is appended to its queue
     Nx.hlist = P.hub_list != HL_OFF;                        // and its hubs to its hub list
+    Nx.filt = 0;
     C->st[1] = Nx;
     C->parity = 1;
 }
@@ -1339,6 +1441,12 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
     const long long w0 = min((long long)blockIdx.x * per, P.W);
     const long long w1 = min(w0 + per, P.W);
     const long long v0 = w0 << 6, v1 = min(w1 << 6, P.n);
+    if (P.use_filter && blockIdx.x == 0)
+        for (int w = threadIdx.x; w < 3 * kFilterWords; w += kBlock) P.filt[w] = 0u;   // no filters yet
+    if (P.count)
+        for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < (long long)P.trace_cap * kCounts;
+             i += (long long)gridDim.x * kBlock)
+            P.pstat[i] = 0ull;
     for (long long w = w0 + threadIdx.x; w < w1; w += kBlock) {
         const unsigned long long rb = (w == rw) ? rbit : 0ull;
         s_next[w - w0] = 0ull;
@@ -1413,7 +1521,9 @@ __global__ void __launch_bounds__(kBlock) bfs_init_root_kernel(Params P, int per
         S.reached_deg = 0;
         S.qform = QF_NONE;
         S.hlist = 0;
-        S.pad[0] = S.pad[1] = 0;
+        S.filt = 0;
+        S.pad1 = 0;
+        S.pad[0] = 0;
         C->level = P.level;
         C->parent = P.parent;
         C->root = root;
@@ -1497,6 +1607,7 @@ hipError_t launch_init(const Params &p, int grid, hipStream_t s)
 
 int layer_build(const Params &p, int layer)
 {
+    if (p.count) return BUILD_COUNTS;
     if (p.td_queue != QM_OFF) return BUILD_QUEUES;
     if (p.hub_list == HL_ALL || p.hub_list == HL_TD) return BUILD_HUBS;
     if (p.hub_list == HL_LAYER0 && layer == 1) return BUILD_HUBS;
@@ -1505,16 +1616,27 @@ int layer_build(const Params &p, int layer)
 
 int finish_build(const Params &p)
 {
+    if (p.count) return BUILD_COUNTS;
     if (p.td_queue != QM_OFF) return BUILD_QUEUES;
     if (p.hub_list == HL_ALL || p.hub_list == HL_TD) return BUILD_HUBS;
     return BUILD_PLAIN;
 }
 
+bool layer_filter(const Params &p, int layer)
+{
+    // the filter of F_2 is written by layer 1 (a small top-down layer from the
+    // root's neighbours) and read by layer 2; the other layers run without
+    // its code and registers
+    return p.wide && p.use_filter && (layer == 1 || layer == 2);
+}
+
 template <int B>
 static void launch_layer_build(const Params &p, int layer, int allow_binned, int grid, hipStream_t s)
 {
-    if (p.wide)
-        hipLaunchKernelGGL(bfs_layer_kernel_wide<B>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    if (p.wide && layer_filter(p, layer))
+        hipLaunchKernelGGL((bfs_layer_kernel_wide<B, true>), dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
+    else if (p.wide)
+        hipLaunchKernelGGL((bfs_layer_kernel_wide<B, false>), dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
     else
         hipLaunchKernelGGL(bfs_layer_kernel<B>, dim3(grid), dim3(kBlock), 0, s, p, layer, allow_binned);
 }
@@ -1522,6 +1644,7 @@ static void launch_layer_build(const Params &p, int layer, int allow_binned, int
 hipError_t launch_layer(const Params &p, int layer, int allow_binned, int grid, hipStream_t s)
 {
     switch (layer_build(p, layer)) {
+    case BUILD_COUNTS: launch_layer_build<BUILD_COUNTS>(p, layer, allow_binned, grid, s); break;
     case BUILD_QUEUES: launch_layer_build<BUILD_QUEUES>(p, layer, allow_binned, grid, s); break;
     case BUILD_HUBS: launch_layer_build<BUILD_HUBS>(p, layer, allow_binned, grid, s); break;
     default: launch_layer_build<BUILD_PLAIN>(p, layer, allow_binned, grid, s); break;
@@ -1562,9 +1685,10 @@ hipError_t launch_root(const Params &p, hipStream_t s)
 hipError_t launch_finish(const Params &p, hipStream_t s)
 {
     switch (finish_build(p)) {
-    case BUILD_QUEUES: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_QUEUES>, dim3(1), dim3(kFinishBlock), 0, s, p); break;
-    case BUILD_HUBS: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_HUBS>, dim3(1), dim3(kFinishBlock), 0, s, p); break;
-    default: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_PLAIN>, dim3(1), dim3(kFinishBlock), 0, s, p); break;
+    case BUILD_COUNTS: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_COUNTS>, dim3(1), dim3(kFinisherBlock), 0, s, p); break;
+    case BUILD_QUEUES: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_QUEUES>, dim3(1), dim3(kFinisherBlock), 0, s, p); break;
+    case BUILD_HUBS: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_HUBS>, dim3(1), dim3(kFinisherBlock), 0, s, p); break;
+    default: hipLaunchKernelGGL(bfs_finish_kernel<BUILD_PLAIN>, dim3(1), dim3(kFinisherBlock), 0, s, p); break;
     }
     return hipGetLastError();
 }
@@ -1579,17 +1703,26 @@ hipError_t launch_iso_template(const long long *off, long long n, long long W,
 }
 
 void *kernel_ptr_init() { return (void *)bfs_init_kernel; }
-void *kernel_ptr_layer(bool wide, int build)
+template <int B>
+static void *layer_ptr(bool wide, bool filter)
+{
+    if (!wide) return (void *)bfs_layer_kernel<B>;
+    return filter ? (void *)bfs_layer_kernel_wide<B, true> : (void *)bfs_layer_kernel_wide<B, false>;
+}
+
+void *kernel_ptr_layer(bool wide, int build, bool filter)
 {
     switch (build) {
-    case BUILD_QUEUES: return wide ? (void *)bfs_layer_kernel_wide<BUILD_QUEUES> : (void *)bfs_layer_kernel<BUILD_QUEUES>;
-    case BUILD_HUBS: return wide ? (void *)bfs_layer_kernel_wide<BUILD_HUBS> : (void *)bfs_layer_kernel<BUILD_HUBS>;
-    default: return wide ? (void *)bfs_layer_kernel_wide<BUILD_PLAIN> : (void *)bfs_layer_kernel<BUILD_PLAIN>;
+    case BUILD_COUNTS: return layer_ptr<BUILD_COUNTS>(wide, filter);
+    case BUILD_QUEUES: return layer_ptr<BUILD_QUEUES>(wide, filter);
+    case BUILD_HUBS: return layer_ptr<BUILD_HUBS>(wide, filter);
+    default: return layer_ptr<BUILD_PLAIN>(wide, filter);
     }
 }
 void *kernel_ptr_finish(int build)
 {
     switch (build) {
+    case BUILD_COUNTS: return (void *)bfs_finish_kernel<BUILD_COUNTS>;
     case BUILD_QUEUES: return (void *)bfs_finish_kernel<BUILD_QUEUES>;
     case BUILD_HUBS: return (void *)bfs_finish_kernel<BUILD_HUBS>;
     default: return (void *)bfs_finish_kernel<BUILD_PLAIN>;
@@ -1600,7 +1733,7 @@ int layer_blocks_per_cu(bool wide)
 {
     int occ = 0;
     const hipError_t e =
-        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel_wide<BUILD_PLAIN>, kBlock, 0)
+        wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel_wide<BUILD_PLAIN, false>, kBlock, 0)
              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bfs_layer_kernel<BUILD_PLAIN>, kBlock, 0);
     return e == hipSuccess ? occ : -1;
 }

@@ -99,6 +99,9 @@ int validate_options(const bfs_options &o)
     if (o.bu_serial_probes < -1 || o.bu_serial_probes > 1)
         return set_error(BFS_E_INVALID, "bu_serial_probes must be -1, 0 or 1");
     if (o.td_queue < -1 || o.td_queue > 2) return set_error(BFS_E_INVALID, "td_queue must be -1, 0, 1 or 2");
+    if (o.alpha_binned < 0) return set_error(BFS_E_INVALID, "alpha_binned must be >= 0");
+    if (o.bu_filter < -1 || o.bu_filter > 1) return set_error(BFS_E_INVALID, "bu_filter must be -1, 0 or 1");
+    if (o.count_work < 0 || o.count_work > 1) return set_error(BFS_E_INVALID, "count_work must be 0 or 1");
     if (o.td_hub_list < -1 || o.td_hub_list > 3)
         return set_error(BFS_E_INVALID, "td_hub_list must be in [-1, 3]");
     if (o.graph_launch < 0 || o.graph_launch > 1 || o.profile_layers < 0 || o.profile_layers > 1 ||
@@ -113,6 +116,7 @@ Workspace::~Workspace()
     if (dbuf) hipFree(dbuf);
     if (bin_buf) hipFree(bin_buf);
     if (q_buf) hipFree(q_buf);
+    if (pstat) hipFree(pstat);
     if (hq_buf) hipFree(hq_buf);
     if (out_tmp) hipFree(out_tmp);
     if (h_ctrl) hipHostFree(h_ctrl);
@@ -131,7 +135,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static size_t workspace_bytes(long long W)
 {
     return align256((size_t)W * 8) + align256((size_t)W * 8 * 3) + align256(sizeof(Ctrl)) +
-           align256((size_t)kTraceCap * sizeof(LayerRec));
+           align256((size_t)kTraceCap * sizeof(LayerRec)) + align256((size_t)3 * kFilterWords * 4);
 }
 
 int get_workspace(Graph *g, void *stream, Workspace **out)
@@ -164,7 +168,8 @@ int get_workspace(Graph *g, void *stream, Workspace **out)
     w->vis = (unsigned long long *)(b + o);  o += align256((size_t)W * 8);
     w->bm = (unsigned long long *)(b + o);   o += align256((size_t)W * 8 * 3);
     w->ctrl = (Ctrl *)(b + o);               o += align256(sizeof(Ctrl));
-    w->trace = (LayerRec *)(b + o);
+    w->trace = (LayerRec *)(b + o);          o += align256((size_t)kTraceCap * sizeof(LayerRec));
+    w->filt = (unsigned *)(b + o);
     if ((e = hipMemset(w->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return hip_fail(e, "workspace init");
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "workspace init");
     *out = w.get();
@@ -249,6 +254,8 @@ static int ensure_bins(Graph *g, Workspace *w)
 //    296 -> 297, SCALE 20 146 -> 143.  So it is on where the table is large
 //    (graphs in the wide build of the layer kernel).
 constexpr int kDefaultQueueMode = QM_OFF;
+// Membership filters of small frontiers on by default.
+constexpr bool kDefaultFilter = true;
 
 void queue_modes(const Graph *g, const bfs_options &opt, int *td_queue, int *hub_list)
 {
@@ -312,10 +319,17 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->bm = w->bm;
     P->ctrl = w->ctrl;
     P->trace = w->trace;
+    P->filt = w->filt;
+    // filters are built into the wide layer kernel only (graphs whose frontier
+    // bitmap does not fit in the L2)
+    P->use_filter = g->wide && (opt.bu_filter > 0 || (opt.bu_filter == 0 && kDefaultFilter));
+    P->pstat = w->pstat;
+    P->count = opt.count_work && w->pstat ? 1 : 0;
     P->trace_cap = w->trace ? kTraceCap : 0;   // no trace without a buffer for it
     P->rule = opt.rule;
     P->alpha = opt.alpha;
     P->beta = opt.beta;
+    P->alpha_bin = opt.alpha_binned > 0 ? opt.alpha_binned : opt.alpha;
     P->first_writer = opt.first_writer;
     P->async_run = opt.async;
     P->serial_probes = opt.bu_serial_probes > 0 || (opt.bu_serial_probes == 0 && g->n >= (1LL << 24));
@@ -429,8 +443,9 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
     char key[160];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", opt.rule, opt.alpha, opt.beta, opt.probe_k,
-             P.wpg, P.wpg_td, P.hub_deg, P.first_writer, P.serial_probes, grid, L, P.td_queue, P.hub_list);
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%lld", opt.rule, opt.alpha, opt.beta,
+             opt.probe_k, P.wpg, P.wpg_td, P.hub_deg, P.first_writer, P.serial_probes, grid, L, P.td_queue,
+             P.hub_list, P.alpha_bin);
     hipError_t e;
     auto it = w->replays.find(key);
     if (it == w->replays.end()) {
@@ -456,7 +471,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         int no_bins = 0;   // the captured sequence has no binned kernels
         for (int i = 0; i < L; ++i) {
             void *args[] = {&R.params, &layer_idx[i], &no_bins};
-            kp.func = kernel_ptr_layer(R.params.wide != 0, layer_build(R.params, i));
+            kp.func = kernel_ptr_layer(R.params.wide != 0, layer_build(R.params, i), layer_filter(R.params, i));
             kp.kernelParams = args;
             hipGraphNode_t node;
             if ((e = hipGraphAddKernelNode(&node, R.graph, &prev, 1, &kp)) != hipSuccess)
@@ -466,7 +481,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         void *fin_args[] = {&R.params};
         kp.func = kernel_ptr_finish(finish_build(R.params));
         kp.gridDim = dim3(1);
-        kp.blockDim = dim3(kFinishBlock);
+        kp.blockDim = dim3(kFinisherBlock);
         kp.kernelParams = fin_args;
         hipGraphNode_t fin;
         if ((e = hipGraphAddKernelNode(&fin, R.graph, &prev, 1, &kp)) != hipSuccess)
@@ -768,6 +783,7 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
     if (!level_out || !parent_out) return set_error(BFS_E_INVALID, "NULL output");
     if (opt.async && (!opt.out_on_device || stats))
         return set_error(BFS_E_INVALID, "async runs need device outputs and no stats");
+    if (opt.count_work && !stats) return set_error(BFS_E_INVALID, "count_work needs stats");
 
     Workspace *w = nullptr;
     rc = get_workspace(g, opt.stream, &w);
@@ -775,6 +791,9 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
     std::lock_guard<std::mutex> wl(w->mu);
     hipStream_t s = (hipStream_t)opt.stream;
     hipError_t e;
+    if (opt.count_work && !w->pstat &&
+        (e = hipMalloc(&w->pstat, (size_t)kTraceCap * kCounts * 8)) != hipSuccess)
+        return hip_fail(e, "work counters");
 
     int *lvl = level_out, *par = parent_out;
     if (!opt.out_on_device) {
@@ -847,9 +866,16 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
             const int ncopy = std::min(nrec, stats->capacity);
             e = hipMemcpy(w->h_trace, w->trace, nrec * sizeof(LayerRec), hipMemcpyDeviceToHost);
             if (e != hipSuccess) return hip_fail(e, "trace copy");
+            std::vector<unsigned long long> work;
+            if (opt.count_work) {
+                work.resize((size_t)ncopy * kCounts);
+                e = hipMemcpy(work.data(), w->pstat, work.size() * 8, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) return hip_fail(e, "work counter copy");
+            }
             for (int i = 0; i < ncopy; ++i) {
                 const LayerRec &r = w->h_trace[i];
                 bfs_layer_stat &o = stats->layers[i];
+                for (int k = 0; k < 6; ++k) o.work[k] = (k < kCounts && !work.empty()) ? (int64_t)work[i * kCounts + k] : 0;
                 o.direction = r.dir;
                 o.reserved = 0;
                 o.n_f = r.n_f;

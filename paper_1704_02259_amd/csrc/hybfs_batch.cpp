@@ -260,6 +260,7 @@ int bfs_run_batch(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t *leve
                 o.v_u = r.v_u;
                 o.kernel_us = (profile && i < launched) ? kus[i] : 0.0;
                 o.t_us = o.kernel_us;
+                for (int k = 0; k < 6; ++k) o.work[k] = 0;
             }
         }
     }

@@ -39,6 +39,8 @@ struct Workspace {
     unsigned long long *bm = nullptr;
     Ctrl *ctrl = nullptr;
     LayerRec *trace = nullptr;
+    unsigned *filt = nullptr;     // three membership filters of small frontiers
+    unsigned long long *pstat = nullptr;   // per-layer work counters (count_work), on first use
     int *out_tmp = nullptr;       // level + parent staging for host outputs
     long long out_tmp_n = 0;
     Ctrl *h_ctrl = nullptr;       // pinned

@@ -25,7 +25,8 @@ constexpr size_t kVisOff = 0;
 constexpr size_t kBmOff = al256((size_t)kNoAllocMaxWords * 8);
 constexpr size_t kCtrlOff = kBmOff + al256((size_t)kNoAllocMaxWords * 8 * 3);
 constexpr size_t kTraceOff = kCtrlOff + al256(sizeof(Ctrl));
-constexpr size_t kScratchBytes = kTraceOff + al256((size_t)kTraceCap * sizeof(LayerRec));
+constexpr size_t kFiltOff = kTraceOff + al256((size_t)kTraceCap * sizeof(LayerRec));
+constexpr size_t kScratchBytes = kFiltOff + al256((size_t)3 * kFilterWords * 4);
 constexpr int kMaxDevices = 64;
 
 }  // namespace
@@ -62,6 +63,7 @@ int noalloc_setup(NoAllocDevice &D, hipStream_t s)
     w.bm = (unsigned long long *)(b + kBmOff);
     w.ctrl = (Ctrl *)(b + kCtrlOff);
     w.trace = (LayerRec *)(b + kTraceOff);
+    w.filt = (unsigned *)(b + kFiltOff);
     w.bytes = kScratchBytes;
     w.no_alloc = true;   // no frontier queues or hub lists either
     if ((e = hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), s)) != hipSuccess ||
@@ -158,6 +160,7 @@ extern "C" int bfs_run_noalloc(bfs_graph_t gh, int32_t root, int32_t *level_out,
                     o.v_u = r.v_u;
                     o.kernel_us = 0.0;
                     o.t_us = 0.0;
+                    for (int k = 0; k < 6; ++k) o.work[k] = 0;
                 }
             }
         }

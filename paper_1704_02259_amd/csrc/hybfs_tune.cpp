@@ -131,6 +131,7 @@ int bfs_autotune(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t mode, 
         knobs.push_back({&bfs_options::probe_k, {0, 2, 4, 8, 16, 32}});
         knobs.push_back({&bfs_options::td_hub_degree, {256, 1024, 4096, 16384}});
         knobs.push_back({&bfs_options::bu_serial_probes, {0, 1, -1}});
+        if (g->bin_auto) knobs.push_back({&bfs_options::alpha_binned, {0, 2, 4, 6, 8, 14}});
     }
 
     double best_us = 0.0;

@@ -41,13 +41,15 @@ class bfs_options(ctypes.Structure):
                 ("graph_launch", ctypes.c_int32), ("td_binned", ctypes.c_int32),
                 ("first_writer", ctypes.c_int32), ("bu_serial_probes", ctypes.c_int32),
                 ("td_queue", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("td_hub_list", ctypes.c_int32), ("reserved4", ctypes.c_int32)]
+                ("td_hub_list", ctypes.c_int32), ("alpha_binned", ctypes.c_int32),
+                ("bu_filter", ctypes.c_int32), ("count_work", ctypes.c_int32)]
 
 
 class bfs_layer_stat(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("n_f", ctypes.c_int64), ("m_f", ctypes.c_int64), ("m_u", ctypes.c_int64),
-                ("v_u", ctypes.c_int64), ("t_us", ctypes.c_double), ("kernel_us", ctypes.c_double)]
+                ("v_u", ctypes.c_int64), ("t_us", ctypes.c_double), ("kernel_us", ctypes.c_double),
+                ("work", ctypes.c_int64 * 6)]
 
 
 class bfs_stats(ctypes.Structure):
@@ -90,7 +92,7 @@ class bfs_tune_report(ctypes.Structure):
 
 
 OPTION_KNOBS = ("rule", "alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks", "words_per_wave",
-                "layers_per_launch", "td_binned", "bu_serial_probes", "td_queue", "td_hub_list")
+                "layers_per_launch", "td_binned", "bu_serial_probes", "td_queue", "td_hub_list", "alpha_binned", "bu_filter")
 
 
 class HybfsError(RuntimeError):
@@ -220,7 +222,7 @@ def stats_layers(st: bfs_stats, arr) -> list[dict]:
     for i in range(min(st.num_layers, st.capacity)):
         r = arr[i]
         out.append({"dir": r.direction, "n_f": r.n_f, "m_f": r.m_f, "m_u": r.m_u, "v_u": r.v_u,
-                    "t_us": r.t_us, "kernel_us": r.kernel_us})
+                    "t_us": r.t_us, "kernel_us": r.kernel_us, "work": list(r.work)})
     return out
 
 

@@ -212,6 +212,7 @@ def test_wide_layer_kernel(torch, hyb):
     r = int(inputs.pick_roots(g, 1, 11)[0])
     for mode in (dict(td_queue=1, td_hub_list=1), dict(td_queue=2)):
         _say("er24", r, mode)
-        lv, pa, st = _gpu_bfs(torch, G, r, **mode)
+        # alpha_binned = alpha: the direction trace follows the plain edge rule
+        lv, pa, st = _gpu_bfs(torch, G, r, alpha_binned=14, **mode)
         _check_against_oracle(g, r, lv, pa, st)
     G.close()
