@@ -372,6 +372,112 @@ def layer_table(G, g, root, kw, torch, dev):
     return {"root": int(root), "layers": rows, "total_us": round(st["device_us"], 1)}
 
 
+def layer_profile(torch, hybfs, dev, workload, nroots, kw, out_path):
+    """Per-layer profile of the first nroots roots of a workload, for the
+    analogue of the paper's Tables 4-7 with hardware counters.  First one
+    plain traversal per root (the dispatches a rocprofv3 counter run of this
+    command attributes to layers, in launch order), then per root: HIP-event
+    time of each layer's kernels, the layer's work counts (count_work) and
+    the oracle's algorithmic bytes of either direction.  Writes the layer map
+    (JSON) that join_layer_counters reads."""
+    import inputs
+    import oracle
+    g = inputs.workload_graph(workload)
+    roots = [int(r) for r in inputs.workload_roots(workload, g, nroots)]
+    G = hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID)
+    lv = torch.empty(g.n, dtype=torch.int32, device=dev)
+    pa = torch.empty(g.n, dtype=torch.int32, device=dev)
+    launches = []
+    for r in roots:
+        _, _, st = G.run(r, lv, pa, stats=True, **kw)
+        torch.cuda.synchronize()
+        launches.append({"root": r, "layer0_kernel": st["layer0_kernel"], "layer_launches": st["layer_launches"],
+                         "num_layers": st["num_layers"]})
+    info = G.info()
+    out = {"workload": workload, "options": kw, "n": g.n, "nnz": g.nnz, "binned_kernels": None, "roots": []}
+    for r, la in zip(roots, launches):
+        _, _, st = G.run(r, lv, pa, stats=True, profile_layers=1, **kw)
+        _, _, sc = G.run(r, lv, pa, stats=True, count_work=1, **kw)
+        elv, _ = oracle.bfs(g, r)
+        ab = oracle.algorithmic_bytes(g, elv)
+        rows = []
+        for d, (x, c) in enumerate(zip(st["layers"], sc["layers"])):
+            td, bu = ab["per_layer"][d] if d < len(ab["per_layer"]) else (0, 0)
+            rows.append({"layer": d, "dir": "BU" if x["dir"] else "TD", "n_f": x["n_f"], "m_f": x["m_f"],
+                         "us": round(x["kernel_us"], 1), "td_bytes": td, "bu_bytes": bu, "work": c["work"]})
+        out["roots"].append({**la, "layers": rows})
+        log(f"layer profile root {r}: {len(rows)} layers")
+        del elv
+    out["layer_kernel"] = "bfs_layer_kernel_wide" if info.layer_kernel_wide else "bfs_layer_kernel"
+    with open(out_path, "w") as f:
+        json.dump(out, f)
+    G.close()
+    return out
+
+
+def _read_counter_csv(path):
+    """Per-dispatch counter values of a rocprofv3 --pmc CSV: {dispatch id:
+    (kernel name, {counter: value})}."""
+    import csv
+    rows = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            did = int(r["Dispatch_Id"])
+            name = r["Kernel_Name"]
+            ent = rows.setdefault(did, (name, {}))
+            ent[1][r["Counter_Name"]] = ent[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return rows
+
+
+def join_layer_counters(map_path, csv_paths, fetch_factor=2.0, write_factor=1.0):
+    """Attribute rocprofv3 per-dispatch counters (FETCH_SIZE, WRITE_SIZE,
+    TCC_HIT_sum, TCC_MISS_sum; KiB for the first two, scaled by the factors a
+    plain device copy gives) to the layers of the traversals layer_profile
+    ran first, by launch order: a traversal starts at its initialisation
+    kernel; layer i's dispatches are its layer kernel and the binned kernels
+    enqueued after it.  Returns the layer map with per-layer bytes and L2 hit
+    rates."""
+    with open(map_path) as f:
+        lm = json.load(f)
+    disp = {}
+    for p in csv_paths:
+        for did, (name, cnt) in _read_counter_csv(p).items():
+            ent = disp.setdefault(did, [name, {}])
+            ent[1].update(cnt)
+    order = sorted(disp)
+    trav = []
+    for did in order:
+        name, cnt = disp[did]
+        if "init" in name and ("bfs_init_kernel" in name or "bfs_init_root_kernel" in name):
+            trav.append([])
+        elif trav and ("bfs_" in name):
+            trav[-1].append((name, cnt))
+    for ri, root in enumerate(lm["roots"]):
+        if ri >= len(trav):
+            break
+        seq = trav[ri]
+        first = 1 if root["layer0_kernel"] else 0
+        layer = first - 1
+        per = {}
+        for name, cnt in seq:
+            if "layer_kernel" in name:
+                layer += 1
+            elif "finish" in name or "root_kernel" in name:
+                continue
+            acc = per.setdefault(layer, {"FETCH_SIZE": 0.0, "WRITE_SIZE": 0.0, "TCC_HIT_sum": 0.0, "TCC_MISS_sum": 0.0})
+            for k in acc:
+                acc[k] += cnt.get(k, 0.0)
+        for row in root["layers"]:
+            c = per.get(row["layer"])
+            if c is None:
+                continue
+            row["fetch_bytes"] = c["FETCH_SIZE"] * 1024 * fetch_factor
+            row["write_bytes"] = c["WRITE_SIZE"] * 1024 * write_factor
+            hm = c["TCC_HIT_sum"] + c["TCC_MISS_sum"]
+            row["l2_hit"] = round(c["TCC_HIT_sum"] / hm, 3) if hm else None
+    return lm
+
+
 def cpu_description() -> dict:
     """Host cores and CPU model of the machine the oracle runs on."""
     model = None
@@ -691,7 +797,30 @@ def main():
                     help="skip the host-output leg (runs that include the device-to-host copy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--layer-profile", type=int, default=0,
+                    help="only the per-layer profile of this many roots of --workload (writes --layer-map)")
+    ap.add_argument("--layer-map", default="gpurun_out/layer_map.json")
+    ap.add_argument("--join-counters", nargs="*", default=None,
+                    help="host only: join rocprofv3 --pmc CSVs with --layer-map; prints a markdown table")
     args = ap.parse_args()
+
+    if args.join_counters is not None:
+        lm = join_layer_counters(args.layer_map, args.join_counters)
+        print(f"{lm['workload']}, options {lm['options']}, layer kernel {lm['layer_kernel']}")
+        print("| root | layer | dir | n_f | m_f | us | alg. bytes (dir taken) | HBM read | HBM write | "
+              "hw/alg | L2 hit | work |")
+        print("|---|---|---|---|---|---|---|---|---|---|---|---|")
+        for root in lm["roots"]:
+            for row in root["layers"]:
+                alg = row["bu_bytes"] if row["dir"] == "BU" else row["td_bytes"]
+                fb, wb = row.get("fetch_bytes"), row.get("write_bytes")
+                hw = (fb + wb) if fb is not None else None
+                print(f"| {root['root']} | {row['layer']} | {row['dir']} | {row['n_f']} | {row['m_f']} | "
+                      f"{row['us']} | {alg / 1e6:.2f} MB | "
+                      f"{'' if fb is None else f'{fb / 1e6:.1f} MB'} | {'' if wb is None else f'{wb / 1e6:.1f} MB'} | "
+                      f"{'' if hw is None or not alg else f'{hw / alg:.1f}'} | {row.get('l2_hit', '')} | "
+                      f"{row['work']} |")
+        return
 
     if args.copy_calibration:
         import torch
@@ -723,6 +852,15 @@ def main():
     if args.sweep:
         print(json.dumps({"sweep": sweep(torch, hybfs, dev), "unit": "harmonic-mean GTEPS",
                           "data": "synthetic"}), flush=True)
+        return
+    if args.layer_profile:
+        kw = {}
+        if args.words_per_wave:
+            kw["words_per_wave"] = args.words_per_wave
+        if args.alpha:
+            kw["alpha"] = args.alpha
+        out = layer_profile(torch, hybfs, dev, args.workload, args.layer_profile, kw, args.layer_map)
+        print(json.dumps({"layer_profile": args.workload, "roots": len(out["roots"]), "map": args.layer_map}))
         return
 
     main_leg, g = single_root_leg(torch, hybfs, dev, args.workload, args, args.roots, args.cpu_seconds,

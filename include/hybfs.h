@@ -198,8 +198,10 @@ typedef struct bfs_options {
                                   the table is abandoned for the table).  1 = every
                                   step keeps them; 2 = only layer 0 (the root's
                                   row), for layer 1; 3 = layer 0 and the top-down
-                                  steps; -1 = never; 0 (default) = the library's
-                                  choice */
+                                  steps; 4 = layer 0 and a top-down layer 1, for
+                                  layers 1 and 2; -1 = never; 0 (default) = the
+                                  library's choice (2 on graphs of 2^24 vertices and
+                                  more, else -1) */
     int32_t alpha_binned;      /* edge rule for a layer whose top-down step would run
                                   binned (td_binned): stay top-down while
                                   m_f * alpha_binned <= m_u, even where alpha says

@@ -168,7 +168,8 @@ __device__ __forceinline__ Item *hubs_of(const Params &P, int d) { return (d & 1
 enum { HL_OFF = 0,
        HL_ALL = 1,                       // every step lists the hubs it discovers
        HL_LAYER0 = 2,                    // only layer 0 (the root's row) does, for layer 1
-       HL_TD = 3 };                      // layer 0 and the top-down steps do
+       HL_TD = 3,                        // layer 0 and the top-down steps do
+       HL_EARLY = 4 };                   // layer 0 and a top-down layer 1 do, for layers 1 and 2
 
 // Builds of the layer kernel (which lists their code keeps; the last one
 // counts the work of each layer instead).

@@ -942,7 +942,8 @@ __device__ __forceinline__ bool run_layer(const Params &Pin, int parity, long lo
     }
     // this layer also writes F_{d+1} as a queue, and lists its hubs
     P.q_write = P.td_queue == QM_ALL || (P.td_queue == QM_TOPDOWN && cur == DIR_TD && !binned);
-    P.h_write = P.hub_list == HL_ALL || (P.hub_list == HL_TD && cur == DIR_TD);
+    P.h_write = P.hub_list == HL_ALL || (P.hub_list == HL_TD && cur == DIR_TD) ||
+                (P.hub_list == HL_EARLY && cur == DIR_TD && d == 1 && !binned);
     // a small top-down layer fills its output's membership filter, which a
     // bottom-up layer with a small frontier uses (in the LDS of the tile
     // histogram, so not in the finisher, which has none)
@@ -1611,6 +1612,7 @@ int layer_build(const Params &p, int layer)
     if (p.td_queue != QM_OFF) return BUILD_QUEUES;
     if (p.hub_list == HL_ALL || p.hub_list == HL_TD) return BUILD_HUBS;
     if (p.hub_list == HL_LAYER0 && layer == 1) return BUILD_HUBS;
+    if (p.hub_list == HL_EARLY && (layer == 1 || layer == 2)) return BUILD_HUBS;
     return BUILD_PLAIN;
 }
 

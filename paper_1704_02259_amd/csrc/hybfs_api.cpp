@@ -102,8 +102,8 @@ int validate_options(const bfs_options &o)
     if (o.alpha_binned < 0) return set_error(BFS_E_INVALID, "alpha_binned must be >= 0");
     if (o.bu_filter < -1 || o.bu_filter > 1) return set_error(BFS_E_INVALID, "bu_filter must be -1, 0 or 1");
     if (o.count_work < 0 || o.count_work > 1) return set_error(BFS_E_INVALID, "count_work must be 0 or 1");
-    if (o.td_hub_list < -1 || o.td_hub_list > 3)
-        return set_error(BFS_E_INVALID, "td_hub_list must be in [-1, 3]");
+    if (o.td_hub_list < -1 || o.td_hub_list > 4)
+        return set_error(BFS_E_INVALID, "td_hub_list must be in [-1, 4]");
     if (o.graph_launch < 0 || o.graph_launch > 1 || o.profile_layers < 0 || o.profile_layers > 1 ||
         o.async < 0 || o.async > 1 || o.out_on_device < 0 || o.out_on_device > 1)
         return set_error(BFS_E_INVALID, "flag options must be 0 or 1");

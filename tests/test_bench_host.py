@@ -60,3 +60,41 @@ def test_more_than_one_gpu_is_refused():
     line = [l for l in res.stdout.splitlines() if l.startswith("{")][-1]
     out = json.loads(line)
     assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+def test_join_layer_counters_attributes_dispatches_by_launch_order(tmp_path):
+    """Two traversals: the first with layer 0 in the initialisation kernel and
+    two binned kernels after layer 1, the second with layer 0 in the layer
+    kernel.  Dispatches of other kernels, a finisher and the later statistics
+    traversals are ignored; counters of a layer sum its kernels."""
+    lm = {"workload": "w", "options": {}, "layer_kernel": "bfs_layer_kernel",
+          "roots": [{"root": 5, "layer0_kernel": 2, "layer_launches": 2, "num_layers": 3,
+                     "layers": [{"layer": d, "dir": "TD", "n_f": 1, "m_f": 1, "us": 1.0, "td_bytes": 10,
+                                 "bu_bytes": 20, "work": [0] * 6} for d in range(3)]},
+                    {"root": 7, "layer0_kernel": 0, "layer_launches": 2, "num_layers": 2,
+                     "layers": [{"layer": d, "dir": "BU", "n_f": 1, "m_f": 1, "us": 1.0, "td_bytes": 10,
+                                 "bu_bytes": 20, "work": [0] * 6} for d in range(2)]}]}
+    mp = tmp_path / "map.json"
+    mp.write_text(json.dumps(lm))
+    seq = ["__amd_rocclr_fillBufferAligned", "hybfs::bfs_init_root_kernel(hybfs::Params, int)",
+           "void hybfs::bfs_layer_kernel<0>(hybfs::Params, int, int)",
+           "hybfs::bfs_bin_scan_kernel(hybfs::Params, int)", "hybfs::bfs_bin_scatter_kernel(hybfs::Params, int)",
+           "void hybfs::bfs_layer_kernel<0>(hybfs::Params, int, int)", "void hybfs::bfs_finish_kernel<0>(hybfs::Params)",
+           "hybfs::bfs_init_kernel(hybfs::Params)", "void hybfs::bfs_layer_kernel<0>(hybfs::Params, int, int)",
+           "void hybfs::bfs_layer_kernel<0>(hybfs::Params, int, int)", "void hybfs::bfs_finish_kernel<0>(hybfs::Params)",
+           "hybfs::bfs_init_root_kernel(hybfs::Params, int)", "void hybfs::bfs_layer_kernel<3>(hybfs::Params, int, int)"]
+    lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    for i, name in enumerate(seq):
+        lines.append(f'{i + 1},"{name}",FETCH_SIZE,{i + 1}')
+        lines.append(f'{i + 1},"{name}",TCC_HIT_sum,3')
+        lines.append(f'{i + 1},"{name}",TCC_MISS_sum,1')
+    cp = tmp_path / "c.csv"
+    cp.write_text("\n".join(lines) + "\n")
+    out = bench.join_layer_counters(str(mp), [str(cp)], fetch_factor=2.0)
+    r0, r1 = out["roots"]
+    assert "fetch_bytes" not in r0["layers"][0]                  # layer 0 ran in the init kernel
+    assert r0["layers"][1]["fetch_bytes"] == (3 + 4 + 5) * 1024 * 2.0   # layer kernel + two binned kernels
+    assert r0["layers"][2]["fetch_bytes"] == 6 * 1024 * 2.0
+    assert r1["layers"][0]["fetch_bytes"] == 9 * 1024 * 2.0
+    assert r1["layers"][1]["fetch_bytes"] == 10 * 1024 * 2.0
+    assert r0["layers"][1]["l2_hit"] == 0.75

@@ -11,6 +11,7 @@ equal to the oracle's replay, whatever mode writes and reads the queues:
                 list their edge chunks; top-down layers expand hubs from it
   td_hub_list=2 only layer 0 lists them, for layer 1
   td_hub_list=3 layer 0 and the top-down steps list them
+  td_hub_list=4 layer 0 and a top-down layer 1 list them
 
 Covered: every direction rule on edge-case graphs and Kronecker SCALE 16 and
 20, the binned top-down step, first-writer parents, each placement of layer 0,
@@ -31,9 +32,9 @@ from tests.test_gpu_single import _check_against_oracle, _gpu_bfs, _small_cases
 pytestmark = pytest.mark.gpu
 
 MODES = [dict(td_queue=1), dict(td_queue=2), dict(td_hub_list=1), dict(td_hub_list=2), dict(td_hub_list=3),
-         dict(td_queue=1, td_hub_list=1), dict(td_queue=2, td_hub_list=1), dict(td_queue=1, td_hub_list=2),
-         dict(td_queue=2, td_hub_list=3)]
-MODE_IDS = ["q1", "q2", "hubs", "hubs0", "hubsTD", "q1+hubs", "q2+hubs", "q1+hubs0", "q2+hubsTD"]
+         dict(td_hub_list=4), dict(td_queue=1, td_hub_list=1), dict(td_queue=2, td_hub_list=1),
+         dict(td_queue=1, td_hub_list=2), dict(td_queue=2, td_hub_list=3)]
+MODE_IDS = ["q1", "q2", "hubs", "hubs0", "hubsTD", "hubs01", "q1+hubs", "q2+hubs", "q1+hubs0", "q2+hubsTD"]
 
 
 def _say(*a):
