@@ -317,6 +317,11 @@ void *kernel_ptr_layer(bool wide, int build, bool filter);
 // whether layer `layer` runs in the wide build with the small-frontier filters
 bool layer_filter(const Params &p, int layer);
 void *kernel_ptr_finish(int build);
+void *kernel_ptr_init_root();
+void *kernel_ptr_bin_scan();
+void *kernel_ptr_bin_scatter();
+void *kernel_ptr_bin_reduce();
+constexpr int kReduceBlockThreads = 512;   // threads of a binned reduce block
 int layer_blocks_per_cu(bool wide);
 
 }  // namespace hybfs

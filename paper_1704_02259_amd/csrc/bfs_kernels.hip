@@ -1281,7 +1281,7 @@ __global__ void __launch_bounds__(kBlock) bfs_bin_scatter_kernel(Params P, int l
 
 // Two blocks of this size and their 64 KiB tiles fit one CU, so one tile's
 // loads overlap another's LDS work.
-constexpr int kReduceBlock = 512;
+constexpr int kReduceBlock = kReduceBlockThreads;
 
 // One block per destination tile: the smallest frontier neighbour of every
 // unvisited vertex of the tile by LDS atomic minimum over its bucket, then
@@ -1721,6 +1721,11 @@ void *kernel_ptr_layer(bool wide, int build, bool filter)
     default: return layer_ptr<BUILD_PLAIN>(wide, filter);
     }
 }
+void *kernel_ptr_init_root() { return (void *)bfs_init_root_kernel; }
+void *kernel_ptr_bin_scan() { return (void *)bfs_bin_scan_kernel; }
+void *kernel_ptr_bin_scatter() { return (void *)bfs_bin_scatter_kernel; }
+void *kernel_ptr_bin_reduce() { return (void *)bfs_bin_reduce_kernel; }
+
 void *kernel_ptr_finish(int build)
 {
     switch (build) {

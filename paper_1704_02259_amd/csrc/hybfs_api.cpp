@@ -425,13 +425,21 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     return BFS_OK;
 }
 
-// hipGraph replay of the launch sequence [init, L x layer, finisher].  The
-// graph is built once per workspace and option set; a run only rewrites the
-// init node's arguments (root and output pointers), which the layer kernels
-// pick up from the control block.
+// hipGraph replay of the launch sequence of enqueue_traversal: the
+// initialisation kernel (fused with layer 0 for a root of small degree, as
+// in a direct launch), the layer kernels with the binned top-down kernels
+// after the layers that may bin, and the finisher.  One graph is built per
+// workspace, option set and form of layer 0 (the host knows the root's
+// degree); a run rewrites only the initialisation node's arguments (root and
+// output pointers), which the other kernels pick up from the control block.
 int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl,
-                            int *par, hipStream_t s, int *layers_enqueued)
+                            int *par, hipStream_t s, int *layers_enqueued, int *layer0_kernel)
 {
+    const bool bins = g->nbins <= kMaxBins && (opt.td_binned > 0 || (opt.td_binned == 0 && g->bin_auto));
+    if (bins) {
+        const int rc = ensure_bins(g, w);
+        if (rc) return rc;
+    }
     {
         int qm = QM_OFF, hl = 0;
         queue_modes(g, opt, &qm, &hl);
@@ -442,11 +450,16 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     fill_params(g, w, opt, &P);
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->grid_default;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->depth.typical.load();
-    char key[160];
-    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%lld", opt.rule, opt.alpha, opt.beta,
-             opt.probe_k, P.wpg, P.wpg_td, P.hub_deg, P.first_writer, P.serial_probes, grid, L, P.td_queue,
-             P.hub_list, P.alpha_bin);
+    const long long per = (g->W + grid - 1) / grid;
+    // layer 0 inside the initialisation kernel needs every counter slot at
+    // zero, which a replayed finisher leaves behind
+    const bool fused = g->h_deg[root] <= kRootKernelDegree && per <= kFuseWords && w->counters_zero;
+    char key[200];
+    snprintf(key, sizeof key, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%lld/%d/%d/%d/%d", opt.rule, opt.alpha,
+             opt.beta, opt.probe_k, P.wpg, P.wpg_td, P.hub_deg, P.first_writer, P.serial_probes, grid, L,
+             P.td_queue, P.hub_list, P.alpha_bin, P.use_filter, opt.td_binned, fused ? 1 : 0, bins ? 1 : 0);
     hipError_t e;
+    int per_arg = (int)per;
     auto it = w->replays.find(key);
     if (it == w->replays.end()) {
         Workspace::Replay R;
@@ -454,6 +467,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         R.params.root = root;
         R.params.level = lvl;
         R.params.parent = par;
+        R.fused = fused;
         if ((e = hipGraphCreate(&R.graph, 0)) != hipSuccess) return hip_fail(e, "graph create");
         std::vector<int> layer_idx(L);
         for (int i = 0; i < L; ++i) layer_idx[i] = i;
@@ -461,30 +475,45 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         hipKernelNodeParams kp;
         std::memset(&kp, 0, sizeof kp);
         void *init_args[] = {&R.params};
-        kp.func = kernel_ptr_init();
+        void *init_fused_args[] = {&R.params, &per_arg};
+        kp.func = fused ? kernel_ptr_init_root() : kernel_ptr_init();
         kp.gridDim = dim3(grid);
         kp.blockDim = dim3(kBlock);
-        kp.kernelParams = init_args;
+        kp.kernelParams = fused ? init_fused_args : init_args;
         if ((e = hipGraphAddKernelNode(&R.init, R.graph, nullptr, 0, &kp)) != hipSuccess)
             return hip_fail(e, "graph init node");
         prev = R.init;
-        int no_bins = 0;   // the captured sequence has no binned kernels
-        for (int i = 0; i < L; ++i) {
-            void *args[] = {&R.params, &layer_idx[i], &no_bins};
-            kp.func = kernel_ptr_layer(R.params.wide != 0, layer_build(R.params, i), layer_filter(R.params, i));
-            kp.kernelParams = args;
+        auto add = [&](void *fn, dim3 gd, dim3 bd, void **args) -> hipError_t {
+            hipKernelNodeParams np;
+            std::memset(&np, 0, sizeof np);
+            np.func = fn;
+            np.gridDim = gd;
+            np.blockDim = bd;
+            np.kernelParams = args;
             hipGraphNode_t node;
-            if ((e = hipGraphAddKernelNode(&node, R.graph, &prev, 1, &kp)) != hipSuccess)
+            const hipError_t r = hipGraphAddKernelNode(&node, R.graph, &prev, 1, &np);
+            if (r == hipSuccess) prev = node;
+            return r;
+        };
+        std::vector<int> allow(L);
+        for (int i = fused ? 1 : 0; i < L; ++i) {
+            allow[i] = bins && (opt.td_binned > 0 || (i >= 1 && i <= 5));
+            void *args[] = {&R.params, &layer_idx[i], &allow[i]};
+            if ((e = add(kernel_ptr_layer(R.params.wide != 0, layer_build(R.params, i), layer_filter(R.params, i)),
+                         dim3(grid), dim3(kBlock), args)) != hipSuccess)
                 return hip_fail(e, "graph layer node");
-            prev = node;
+            if (allow[i]) {
+                void *bargs[] = {&R.params, &layer_idx[i]};
+                if ((e = add(kernel_ptr_bin_scan(), dim3(1), dim3(kFinishBlock), bargs)) != hipSuccess ||
+                    (e = add(kernel_ptr_bin_scatter(), dim3(grid), dim3(kBlock), bargs)) != hipSuccess ||
+                    (e = add(kernel_ptr_bin_reduce(), dim3(2 * g->cus), dim3(kReduceBlockThreads), bargs)) !=
+                        hipSuccess)
+                    return hip_fail(e, "graph binned nodes");
+            }
         }
         void *fin_args[] = {&R.params};
-        kp.func = kernel_ptr_finish(finish_build(R.params));
-        kp.gridDim = dim3(1);
-        kp.blockDim = dim3(kFinisherBlock);
-        kp.kernelParams = fin_args;
-        hipGraphNode_t fin;
-        if ((e = hipGraphAddKernelNode(&fin, R.graph, &prev, 1, &kp)) != hipSuccess)
+        if ((e = add(kernel_ptr_finish(finish_build(R.params)), dim3(1), dim3(kFinisherBlock), fin_args)) !=
+            hipSuccess)
             return hip_fail(e, "graph finisher node");
         if ((e = hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0)) != hipSuccess)
             return hip_fail(e, "graph instantiate");
@@ -497,18 +526,20 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
     R.params.async_run = opt.async;
     R.params.fail_injected = root == g->fail_root;
     void *init_args[] = {&R.params};
+    void *init_fused_args[] = {&R.params, &per_arg};
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof kp);
-    kp.func = kernel_ptr_init();
+    kp.func = R.fused ? kernel_ptr_init_root() : kernel_ptr_init();
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(kBlock);
-    kp.kernelParams = init_args;
+    kp.kernelParams = R.fused ? init_fused_args : init_args;
     if ((e = hipGraphExecKernelNodeSetParams(R.exec, R.init, &kp)) != hipSuccess)
         return hip_fail(e, "graph update");
     w->counters_zero = false;
     if ((e = hipGraphLaunch(R.exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
     w->counters_zero = true;   // the replayed finisher clears them
-    if (layers_enqueued) *layers_enqueued = L;
+    if (layers_enqueued) *layers_enqueued = R.fused ? L - 1 : L;
+    if (layer0_kernel) *layer0_kernel = R.fused ? 2 : 0;
     return BFS_OK;
 }
 
@@ -819,7 +850,7 @@ int bfs_run(bfs_graph_t gh, int32_t root, int32_t *level_out, int32_t *parent_ou
     if (!opt.graph_launch || profile)
         rc = enqueue_traversal(g, w, opt, root, lvl, par, s, &launched, profile, &layer0);
     else
-        rc = enqueue_traversal_graph(g, w, opt, root, lvl, par, s, &launched);
+        rc = enqueue_traversal_graph(g, w, opt, root, lvl, par, s, &launched, &layer0);
     if (rc) return rc;
     if (stats && (e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
     if (opt.async) return BFS_OK;

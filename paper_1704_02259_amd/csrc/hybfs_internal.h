@@ -71,6 +71,7 @@ struct Workspace {
         hipGraphExec_t exec = nullptr;
         hipGraphNode_t init = nullptr;
         Params params;
+        bool fused = false;            // layer 0 runs in the initialisation node
     };
     std::map<std::string, Replay> replays;
     ~Workspace();

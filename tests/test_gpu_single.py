@@ -457,3 +457,26 @@ def test_root_kernel_when_ranges_exceed_lds(torch, hyb):
             _check_against_oracle(g, r, lv, pa, st)
             assert st["layer0_kernel"] == (1 if grid == 1 else 2)
     G.close()
+
+
+def test_graph_replay_fused_init_and_binned_nodes(torch, kron16, hyb):
+    """The captured launch sequence runs layer 0 in the initialisation node
+    for roots of small degree (a second graph, with the grid-wide layer 0,
+    for the others) and carries the binned top-down kernels when layers may
+    bin: replays alternating the two graphs, with and without binning, async
+    and sync, all equal to the oracle; layer0_kernel reports the form."""
+    g, G, roots = kron16
+    deg = np.diff(g.off)
+    big = int(np.argmax(deg))
+    lv = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pa = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    seq = [int(roots[0]), big, int(roots[1]), big, int(roots[2])]
+    for tb in (0, 1, -1):
+        for r in seq:
+            G.run(r, lv, pa, async_=1, graph_launch=1, td_binned=tb)
+        hyb.hybfs.bfs_graph_sync(G.handle, torch.cuda.current_stream().cuda_stream)
+        for r in seq:
+            _say("graph replay", r, "binned", tb)
+            a = _gpu_bfs(torch, G, r, graph_launch=1, td_binned=tb)
+            _check_against_oracle(g, r, a[0], a[1], a[2])
+            assert a[2]["layer0_kernel"] == (2 if deg[r] <= 4096 else 0)
