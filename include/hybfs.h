@@ -364,12 +364,19 @@ int bfs_autotune(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t mode, i
  * single query, the batched multi-source traversal (bfs_run_batch) for more
  * (only once enough are queued, see batch_threshold).
  * Queries that arrive while others run wait for the next free slot
- * (continuous batching).  Admission by memory: the traversals in flight hold
- * at most memory_budget device bytes, counting each one's workspace and, for
- * host outputs, its output staging; a batch that does not fit is halved, and
- * a slot waits for running traversals to finish when not even one query
- * fits.  Every answer equals bfs_run's for the same graph and root, byte for
- * byte, whatever else is in flight.
+ * (continuous batching).  Admission by memory: the slots hold at most
+ * memory_budget device bytes.  Charged is everything a slot's traversals
+ * leave allocated: the workspaces cached with each graph for the slot's
+ * stream (single-root workspace, binned top-down buckets, frontier queues
+ * and hub lists, host-output staging; batched workspace) and the slot's
+ * host-output staging of batches, plus, while a traversal runs, what it may
+ * still allocate.  The graphs' own CSR arrays are not charged.  When a
+ * traversal does not fit, idle holdings are released (the slot's own caches
+ * of other graphs first, then other idle slots'), then a batch is halved,
+ * then the slot waits for running traversals to finish; a query that does not
+ * fit with nothing running fails with BFS_E_NOMEM.  Every answer equals
+ * bfs_run's for the same graph and root, byte for byte, whatever else is in
+ * flight.
  */
 typedef struct bfs_server *bfs_server_t;
 
@@ -406,8 +413,8 @@ typedef struct bfs_serve_report {
     int64_t batches;         /* traversals launched (single or batched) */
     int64_t batched_requests;/* queries answered by a traversal of more than one root */
     int64_t admission_waits; /* times a slot waited for memory to free up */
-    int64_t bytes_in_use;    /* device bytes charged by traversals in flight now */
-    int64_t peak_bytes;      /* maximum of bytes_in_use */
+    int64_t bytes_in_use;    /* device bytes the slots hold or have reserved now */
+    int64_t peak_bytes;      /* maximum of bytes_in_use (<= memory_budget) */
     int64_t memory_budget;
     double  p50_us;          /* latency = completion - submission (host monotonic clock), */
     double  p99_us;          /* over completed queries */
@@ -415,6 +422,7 @@ typedef struct bfs_serve_report {
     double  max_us;
     double  traversed_edges; /* sum over completed queries of half the reached degree sum */
     double  gteps;           /* traversed_edges / (last completion - first submission) / 1e9 */
+    int64_t evictions;       /* idle cached workspaces or staging released for admission */
 } bfs_serve_report;
 
 /* Create a server on the current HIP device.  cfg may be NULL (defaults).
@@ -451,7 +459,8 @@ int bfs_serve_stats(bfs_server_t s, bfs_serve_report *out);
  * Errors: BFS_E_INVALID (NULL server). */
 int bfs_serve_reset_stats(bfs_server_t s);
 
-/* Finish every queued and running query, then stop the workers and free the
+/* Finish every queued and running query, then stop the workers, release the
+ * workspaces the server's traversals cached with the graphs, and free the
  * server (graphs are not freed).  Errors: BFS_E_INVALID (NULL server). */
 int bfs_serve_destroy(bfs_server_t s);
 

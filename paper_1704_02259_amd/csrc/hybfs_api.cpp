@@ -221,17 +221,63 @@ int check_async_errors(Graph *g, void *stream)
     return BFS_OK;
 }
 
+size_t Workspace::held() const
+{
+    return (dbuf ? bytes : 0) + (bin_buf ? bin_bytes : 0) + (q_buf ? q_bytes : 0) + (hq_buf ? hq_bytes : 0) +
+           (out_tmp ? (size_t)(out_tmp_n + 64) * 8 : 0) + (pstat ? (size_t)kTraceCap * kCounts * 8 : 0);
+}
+
+size_t held_bytes(Graph *g, void *stream, size_t *single, size_t *batch)
+{
+    std::lock_guard<std::mutex> lk(g->mu);
+    size_t a = 0, b = 0;
+    auto it = g->ws.find(stream);
+    if (it != g->ws.end()) a = it->second->held();
+    auto jt = g->bws.find(stream);
+    if (jt != g->bws.end()) b = jt->second->held();
+    if (single) *single = a;
+    if (batch) *batch = b;
+    return a + b;
+}
+
+void release_workspaces(Graph *g, void *stream)
+{
+    std::unique_ptr<Workspace> a;
+    std::unique_ptr<BatchWorkspace> b;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        auto it = g->ws.find(stream);
+        if (it != g->ws.end()) {
+            a = std::move(it->second);
+            g->ws.erase(it);
+        }
+        auto jt = g->bws.find(stream);
+        if (jt != g->bws.end()) {
+            b = std::move(jt->second);
+            g->bws.erase(jt);
+        }
+    }
+    // the destructors free the device memory outside the graph's lock
+}
+
 // Buckets of the binned top-down step, allocated with the first run that may
 // use them: counts, offsets and cursors per tile, and up to min(nnz, 2^28)
 // (parent, vertex) pairs.
+static size_t bin_bytes(const Graph *g)
+{
+    const long long cap = std::max<long long>(1, std::min<long long>(g->nnz, 1LL << 28));
+    return 3 * align256((size_t)(g->nbins + 1) * 4) + (size_t)cap * 8;
+}
+
 static int ensure_bins(Graph *g, Workspace *w)
 {
     if (w->bin_buf) return BFS_OK;
     const long long cap = std::max<long long>(1, std::min<long long>(g->nnz, 1LL << 28));
     const size_t a = align256((size_t)(g->nbins + 1) * 4);
-    const size_t bytes = 3 * a + (size_t)cap * 8;
+    const size_t bytes = bin_bytes(g);
     hipError_t e;
     if ((e = hipMalloc(&w->bin_buf, bytes)) != hipSuccess) return hip_fail(e, "binned top-down buckets");
+    w->bin_bytes = bytes;
     char *b = (char *)w->bin_buf;
     w->bin_cnt = (int *)b;
     w->bin_off = (int *)(b + a);
@@ -279,6 +325,7 @@ static int ensure_queues(Graph *g, Workspace *w, bool queues, bool hub_lists)
     if (queues && !w->q_buf) {
         const size_t a = align256((size_t)g->n * 4);
         if ((e = hipMalloc(&w->q_buf, 2 * a)) != hipSuccess) return hip_fail(e, "frontier queues");
+        w->q_bytes = 2 * a;
         w->q[0] = (int *)w->q_buf;
         w->q[1] = (int *)((char *)w->q_buf + a);
     }
@@ -286,6 +333,7 @@ static int ensure_queues(Graph *g, Workspace *w, bool queues, bool hub_lists)
         const long long cap = std::max<long long>(g->n_hub, 1);
         const size_t a = align256((size_t)cap * sizeof(Item));
         if ((e = hipMalloc(&w->hq_buf, 2 * a)) != hipSuccess) return hip_fail(e, "hub lists");
+        w->hq_bytes = 2 * a;
         w->hq[0] = (Item *)w->hq_buf;
         w->hq[1] = (Item *)((char *)w->hq_buf + a);
         w->hq_cap = g->n_hub;
@@ -357,6 +405,25 @@ void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Par
     P->hq_cap = w->hq_cap;
     P->q_write = 0;
     P->h_write = 0;
+}
+
+size_t single_run_bytes(Graph *g, void *stream, const bfs_options &opt)
+{
+    std::lock_guard<std::mutex> lk(g->mu);
+    auto it = g->ws.find(stream);
+    const Workspace *w = it != g->ws.end() ? it->second.get() : nullptr;
+    const bool bins = g->nbins <= kMaxBins && (opt.td_binned > 0 || (opt.td_binned == 0 && g->bin_auto));
+    int qm = QM_OFF, hl = 0;
+    queue_modes(g, opt, &qm, &hl);
+    // each part: what the workspace holds, or what the run allocates for it
+    size_t b = w && w->dbuf ? w->bytes : workspace_bytes(g->W);
+    b += w && w->bin_buf ? w->bin_bytes : (bins ? bin_bytes(g) : 0);
+    b += w && w->q_buf ? w->q_bytes : queue_bytes(g, qm != QM_OFF, false);
+    b += w && w->hq_buf ? w->hq_bytes : queue_bytes(g, false, hl != 0);
+    const size_t tmp = w && w->out_tmp ? (size_t)(w->out_tmp_n + 64) * 8 : 0;
+    b += opt.out_on_device ? tmp : std::max(tmp, (size_t)(g->n + 64) * 8);
+    b += (w && w->pstat) || opt.count_work ? (size_t)kTraceCap * kCounts * 8 : 0;
+    return b;
 }
 
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,

@@ -58,6 +58,7 @@ struct Workspace {
     int *bin_cnt = nullptr, *bin_off = nullptr, *bin_cur = nullptr;
     unsigned long long *bin_pairs = nullptr;
     long long bin_cap = 0;
+    size_t bin_bytes = 0, q_bytes = 0, hq_bytes = 0;
     // frontier queues (2 x n ids) and hub lists (2 x hub-table entries),
     // allocated with the first run that uses them
     void *q_buf = nullptr;
@@ -74,6 +75,7 @@ struct Workspace {
         bool fused = false;            // layer 0 runs in the initialisation node
     };
     std::map<std::string, Replay> replays;
+    size_t held() const;          // device bytes this workspace holds
     ~Workspace();
 };
 
@@ -94,6 +96,7 @@ struct BatchWorkspace {
     LayerRec *h_trace = nullptr;         // pinned
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> layer_ev;
+    size_t held() const { return (dbuf ? bytes : 0) + (out_tmp ? (size_t)out_tmp_elems * 4 : 0); }
     ~BatchWorkspace();
 };
 
@@ -159,6 +162,13 @@ size_t queue_bytes(const Graph *g, bool queues, bool hub_lists);
 // record cleared; BFS_OK when there were none.
 int check_async_errors(Graph *g, void *stream);
 size_t batch_workspace_bytes(long long n, long long W);
+// Device bytes the workspaces of g for `stream` hold (single-root and
+// batched, each optionally returned), and their release (the stream must be
+// idle, the workspaces unused); the device bytes the single-root workspace of
+// g on `stream` holds after a bfs_run with these options.
+size_t held_bytes(Graph *g, void *stream, size_t *single, size_t *batch);
+void release_workspaces(Graph *g, void *stream);
+size_t single_run_bytes(Graph *g, void *stream, const bfs_options &opt);
 int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out);
 int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
                   const LanePtrs &out, hipStream_t s, bool profile, int *layers_enqueued);

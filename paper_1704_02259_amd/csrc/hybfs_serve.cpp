@@ -2,16 +2,26 @@
 // and worker slots that each own a HIP stream.  A free slot takes the graph
 // whose oldest request has waited longest, drains up to max_batch of its
 // queued requests into one traversal (bfs_run for one root, the batched
-// multi-source traversal for more), and admits it only when its device
-// footprint fits the memory budget.  Requests that arrive while others run
-// are picked up by the next free slot (continuous batching); slots run
-// concurrently, so their kernels overlap on the device.
+// multi-source traversal for more), and admits it only when the device
+// memory the slots hold after it fits the memory budget.  Requests that
+// arrive while others run are picked up by the next free slot (continuous
+// batching); slots run concurrently, so their kernels overlap on the device.
+//
+// Memory accounting: a slot's traversals leave their workspaces cached with
+// the graph, keyed by the slot's stream (single-root workspace with its
+// binned buckets, queues and output staging; batched workspace), and a slot
+// keeps its host-output staging.  All of it is charged to the budget while
+// held.  Admission charges what a traversal will add to its slot's holdings;
+// when that does not fit, idle holdings are released (the slot's own caches
+// of other graphs first, then other idle slots' caches), then a batch is
+// halved, then the slot waits for running traversals.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <thread>
 #include <unordered_map>
 
@@ -36,6 +46,18 @@ struct WorkerSlot {
     hipStream_t stream = nullptr;
     int *stage = nullptr;          // host-output staging of a batch: level, then parent rows
     long long stage_elems = 0;
+    // a traversal runs on this slot; while it does, the slot's worker owns
+    // stage and the workspaces, and the slot is charged busy_charge: what it
+    // held at admission plus what the traversal may allocate
+    bool busy = false;
+    long long busy_charge = 0;
+    std::map<Graph *, long long> cache;   // device bytes of each graph's workspaces on `stream`
+    long long idle_charge() const
+    {
+        long long u = stage_elems * 4;
+        for (const auto &c : cache) u += c.second;
+        return u;
+    }
 };
 
 struct Server {
@@ -51,9 +73,10 @@ struct Server {
     std::vector<std::thread> workers;
     int running_batches = 0;
     bool stopping = false;
-    long long used = 0, peak = 0;
+    long long used = 0, peak = 0;  // bytes held + reserved by all slots, and its maximum
     // statistics since creation or the last reset
-    long long submitted = 0, completed = 0, failed = 0, batches = 0, batched_requests = 0, admission_waits = 0;
+    long long submitted = 0, completed = 0, failed = 0, batches = 0, batched_requests = 0, admission_waits = 0,
+              evictions = 0;
     std::vector<double> lat_us;
     double te = 0.0;
     bool have_first = false;
@@ -64,6 +87,15 @@ struct Server {
     std::vector<double> t_single_us, t_batch_us;
 
     void worker(int i);
+    void recount()
+    {
+        long long u = 0;
+        for (const WorkerSlot &sl : slots) u += sl.busy ? sl.busy_charge : sl.idle_charge();
+        used = u;
+        peak = std::max(peak, used);
+    }
+    long long need(int i, Graph *g, int k, const bfs_options &opt) const;
+    bool evict_one(int i, Graph *g, bool keep_stage);
     int batch_threshold(int gid) const
     {
         if (cfg.batch_threshold > 0) return cfg.batch_threshold;
@@ -75,9 +107,77 @@ struct Server {
     int run_group(int i, Graph *g, std::vector<Request *> &rq, double *te_out);
 };
 
-static long long single_bytes(const Graph *g, bool host_out)
+// Options of every traversal the server runs (the stream is the slot's).
+static bfs_options serve_options(const bfs_serve_config &cfg, hipStream_t s)
 {
-    return (long long)(g->W * 8 * 4 + sizeof(Ctrl) + kTraceCap * sizeof(LayerRec)) + (host_out ? g->n * 8 + 512 : 0);
+    bfs_options opt;
+    bfs_options_init(&opt);
+    if (cfg.alpha > 0) opt.alpha = cfg.alpha;
+    if (cfg.beta > 0) opt.beta = cfg.beta;
+    opt.stream = s;
+    opt.out_on_device = cfg.out_on_device;
+    return opt;
+}
+
+// Bytes slot i's holdings grow by when it runs k roots of g (lock held).
+long long Server::need(int i, Graph *g, int k, const bfs_options &opt) const
+{
+    const WorkerSlot &sl = slots[i];
+    size_t single = 0, batch = 0;
+    held_bytes(g, sl.stream, &single, &batch);
+    long long after;
+    long long stage = sl.stage_elems * 4;
+    if (k == 1) {
+        after = (long long)single_run_bytes(g, sl.stream, opt) + (long long)batch;
+    } else {
+        after = (long long)single + (long long)(batch ? batch : batch_workspace_bytes(g->n, g->W));
+        // a smaller staging buffer is freed before the larger one is allocated
+        if (!cfg.out_on_device) stage = std::max(stage, 8LL * k * g->n);
+    }
+    auto it = sl.cache.find(g);
+    const long long before = it != sl.cache.end() ? it->second : 0;
+    return std::max(0LL, after - before) + (stage - sl.stage_elems * 4);
+}
+
+// Releases the largest idle holding (lock held; it blocks while the device
+// frees): slot i's caches of graphs other than g, its staging unless
+// keep_stage, then what other idle slots hold.  False when there is none.
+bool Server::evict_one(int i, Graph *g, bool keep_stage)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+        int bs = -1;
+        Graph *bg = nullptr;
+        long long best = 0;
+        for (int j = 0; j < (int)slots.size(); ++j) {
+            const WorkerSlot &sl = slots[j];
+            if ((pass == 0) != (j == i) || sl.busy) continue;
+            for (const auto &c : sl.cache)
+                if ((j != i || c.first != g) && c.second > best) {
+                    best = c.second;
+                    bs = j;
+                    bg = c.first;
+                }
+            if ((j != i || !keep_stage) && sl.stage_elems * 4 > best) {
+                best = sl.stage_elems * 4;
+                bs = j;
+                bg = nullptr;
+            }
+        }
+        if (bs < 0) continue;
+        WorkerSlot &sl = slots[bs];
+        if (bg) {
+            release_workspaces(bg, sl.stream);
+            sl.cache.erase(bg);
+        } else {
+            hipFree(sl.stage);
+            sl.stage = nullptr;
+            sl.stage_elems = 0;
+        }
+        ++evictions;
+        recount();
+        return true;
+    }
+    return false;
 }
 
 // Executes one admitted group on slot i (no lock held).
@@ -86,12 +186,7 @@ int Server::run_group(int i, Graph *g, std::vector<Request *> &rq, double *te_ou
     WorkerSlot &sl = slots[i];
     hipStream_t s = sl.stream;
     const int k = (int)rq.size();
-    bfs_options opt;
-    bfs_options_init(&opt);
-    if (cfg.alpha > 0) opt.alpha = cfg.alpha;
-    if (cfg.beta > 0) opt.beta = cfg.beta;
-    opt.stream = s;
-    opt.out_on_device = cfg.out_on_device;
+    const bfs_options opt = serve_options(cfg, s);
     if (k == 1) {
         bfs_stats st;
         std::memset(&st, 0, sizeof st);
@@ -143,13 +238,6 @@ int Server::run_group(int i, Graph *g, std::vector<Request *> &rq, double *te_ou
     return BFS_OK;
 }
 
-// Device bytes a traversal of k roots of g holds while it runs.
-static long long footprint(const Graph *g, int k, bool host_out)
-{
-    if (k == 1) return single_bytes(g, host_out);
-    return (long long)batch_workspace_bytes(g->n, g->W) + (host_out ? 8LL * k * g->n : 0);
-}
-
 void Server::worker(int i)
 {
     // the server's device for this thread; should that fail, every query
@@ -157,6 +245,7 @@ void Server::worker(int i)
     const hipError_t dev_err = hipSetDevice(dev);
     WorkerSlot &sl = slots[i];
     const bool host_out = !cfg.out_on_device;
+    const bfs_options opt = serve_options(cfg, sl.stream);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         // the graph whose head request is oldest
@@ -175,9 +264,16 @@ void Server::worker(int i)
         // the rest to the other slots
         int k = (int)std::min<size_t>(queues[gid].size(), (size_t)cfg.max_batch);
         if (k > 1 && k < batch_threshold(gid)) k = 1;
-        // admission: the traversals in flight may hold at most memory_budget
-        while (k > 1 && used + footprint(g, k, host_out) > cfg.memory_budget) k = std::max(1, k / 2);
-        const long long F = footprint(g, k, host_out);
+        // admission: the slots may hold at most memory_budget; idle caches
+        // go first, then the batch shrinks
+        long long F = need(i, g, k, opt);
+        while (used + F > cfg.memory_budget) {
+            if (!evict_one(i, g, k > 1 && host_out)) {
+                if (k == 1) break;
+                k = std::max(1, k / 2);
+            }
+            F = need(i, g, k, opt);
+        }
         if (used + F > cfg.memory_budget) {
             if (running_batches == 0) {
                 // nothing in flight will free memory: this request cannot be served
@@ -202,8 +298,9 @@ void Server::worker(int i)
             queues[gid].pop_front();
             rq.back()->state = 1;
         }
-        used += F;
-        peak = std::max(peak, used);
+        sl.busy_charge = sl.idle_charge() + F;
+        sl.busy = true;
+        recount();
         ++running_batches;
         ++batches;
         if (k > 1) batched_requests += k;
@@ -229,7 +326,9 @@ void Server::worker(int i)
         const Clock::time_point t = Clock::now();
 
         lk.lock();
-        used -= F;
+        sl.busy = false;
+        sl.cache[g] = (long long)held_bytes(g, sl.stream, nullptr, nullptr);
+        recount();
         --running_batches;
         for (Request *r : rq) {
             r->state = 2;
@@ -412,6 +511,7 @@ int bfs_serve_stats(bfs_server_t sh, bfs_serve_report *out)
     out->batches = S->batches;
     out->batched_requests = S->batched_requests;
     out->admission_waits = S->admission_waits;
+    out->evictions = S->evictions;
     out->bytes_in_use = S->used;
     out->peak_bytes = S->peak;
     out->memory_budget = S->cfg.memory_budget;
@@ -443,7 +543,8 @@ int bfs_serve_reset_stats(bfs_server_t sh)
     if (!sh) return set_error(BFS_E_INVALID, "NULL server");
     Server *S = reinterpret_cast<Server *>(sh);
     std::lock_guard<std::mutex> lk(S->mu);
-    S->submitted = S->completed = S->failed = S->batches = S->batched_requests = S->admission_waits = 0;
+    S->submitted = S->completed = S->failed = S->batches = S->batched_requests = S->admission_waits =
+        S->evictions = 0;
     S->lat_us.clear();
     S->te = 0.0;
     S->have_first = false;
@@ -466,8 +567,8 @@ int bfs_serve_destroy(bfs_server_t sh)
     for (auto &sl : S->slots) {
         if (sl.stream) hipStreamSynchronize(sl.stream);
         if (sl.stage) hipFree(sl.stage);
-        // workspaces keyed by this stream stay with their graphs and are freed
-        // with them; the stream handle is only a key after this point
+        // the workspaces this slot's traversals left with the graphs
+        for (Graph *g : S->graphs) release_workspaces(g, sl.stream);
         if (sl.stream) hipStreamDestroy(sl.stream);
     }
     delete S;

@@ -83,7 +83,7 @@ class bfs_serve_report(ctypes.Structure):
                                               "batches", "batched_requests", "admission_waits",
                                               "bytes_in_use", "peak_bytes", "memory_budget")] + \
                [(k, ctypes.c_double) for k in ("p50_us", "p99_us", "mean_us", "max_us", "traversed_edges",
-                                               "gteps")]
+                                               "gteps")] + [("evictions", ctypes.c_int64)]
 
 
 class bfs_tune_report(ctypes.Structure):

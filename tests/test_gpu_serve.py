@@ -83,7 +83,9 @@ def test_burst_mix_equals_alone(torch, hyb, graphs):
     assert st["completed"] == len(qs) and st["failed"] == 0
     assert st["batched_requests"] > 0 and st["batches"] < len(qs)
     assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
-    assert st["running"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
+    assert st["running"] == 0 and st["queued"] == 0
+    # what stays charged is what the slots keep cached for the next queries
+    assert 0 < st["bytes_in_use"] <= st["peak_bytes"] <= st["memory_budget"]
     alone = {}
     te = 0.0
     for (gi, r), (lv, pa) in zip(qs, bufs):
@@ -154,6 +156,83 @@ def test_small_budget_forces_admission_waits(torch, hyb, graphs):
     assert ei.value.code == hybfs.BFS_E_NOMEM
     assert S.stats()["failed"] == 1
     S.close()
+
+
+def _device_used(torch):
+    free, total = torch.cuda.mem_get_info()
+    return total - free
+
+
+def test_cached_workspaces_stay_within_budget(torch, hyb, graphs):
+    """A traversal leaves its workspaces cached with the graph for its slot's
+    stream; on a graph of 2^23 vertices they include the binned top-down
+    buckets (hundreds of MiB).  Two such graphs and a small one, three slots
+    and a budget of 1.5 such footprints: caches for both large graphs would
+    exceed it, so a slot that moves from one to the other must release an idle
+    cache or wait.  The charged peak stays within the budget, so does the
+    device memory actually allocated (sampled while the queries run), and
+    destroying the server gives it back."""
+    gs, Gs = graphs
+    big = [inputs.erdos_renyi(1 << 23, 1 << 24, seed=2323 + i) for i in range(2)]
+    Gbig = [hyb.Graph.from_csr(g) for g in big]
+    g16, G16 = gs[3], Gs[3]
+    lives = [np.nonzero(np.diff(g.off) > 0)[0] for g in big + [g16]]
+    rng = np.random.default_rng(23)
+    _alone(torch, G16, int(lives[2][0]))     # kernels loaded before memory is measured
+    slack = 64 << 20                         # allocation granularity, streams' own buffers
+
+    # one slot, one query: the charge is what the traversal left allocated
+    lv = torch.empty(big[0].n, dtype=torch.int32, device="cuda")
+    pa = torch.empty(big[0].n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    S = hyb.hybfs.Server(streams=1)
+    gid = S.add_graph(Gbig[0])
+    u0 = _device_used(torch)
+    S.wait(S.submit(gid, int(lives[0][0]), lv.data_ptr(), pa.data_ptr()))
+    held = S.stats()["bytes_in_use"]
+    grew = _device_used(torch) - u0
+    _say("one query holds", held, "device grew by", grew)
+    assert held > Gbig[0].info().workspace_bytes + (128 << 20)    # the binned buckets are charged
+    assert 0.9 * held <= grew <= held + slack
+    S.close()
+    assert _device_used(torch) - u0 <= slack                     # destroy released the caches
+
+    budget = int(1.5 * held)
+    S = hyb.hybfs.Server(streams=3, max_batch=4, batch_threshold=2, memory_budget=budget)
+    Gall = Gbig + [G16]
+    ids = [S.add_graph(G) for G in Gall]
+    qs = [(i % 3, int(rng.choice(lives[i % 3]))) for i in range(36)]
+    bufs = []
+    for gi, r in qs:
+        n = Gall[gi].n
+        bufs.append((torch.empty(n, dtype=torch.int32, device="cuda"),
+                     torch.empty(n, dtype=torch.int32, device="cuda")))
+    torch.cuda.synchronize()
+    u0 = _device_used(torch)
+    tickets = [S.submit(ids[gi], r, lv.data_ptr(), pa.data_ptr()) for (gi, r), (lv, pa) in zip(qs, bufs)]
+    pending, most = set(tickets), 0
+    deadline = time.time() + 120
+    while pending and time.time() < deadline:
+        most = max(most, _device_used(torch) - u0)
+        for t in list(pending):
+            if S.poll(t):
+                pending.discard(t)
+    assert not pending
+    st = S.stats()
+    _say("cached-workspace stats", st, "sampled device growth", most)
+    assert st["completed"] == len(qs) and st["failed"] == 0
+    assert st["peak_bytes"] <= budget
+    assert st["evictions"] > 0
+    assert most <= budget + slack
+    for (gi, r), (lv, pa) in list(zip(qs, bufs))[:9]:
+        elv, epa = _alone(torch, Gall[gi], r)
+        assert np.array_equal(lv.cpu().numpy(), elv) and np.array_equal(pa.cpu().numpy(), epa), (gi, r)
+    olv, opa = oracle.bfs(big[1], qs[1][1])
+    assert np.array_equal(bufs[1][0].cpu().numpy(), olv) and np.array_equal(bufs[1][1].cpu().numpy(), opa)
+    S.close()
+    del bufs
+    for G in Gbig:
+        G.close()
 
 
 def test_paced_stream_and_poll(torch, hyb, graphs):
