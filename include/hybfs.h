@@ -306,8 +306,11 @@ int bfs_run(bfs_graph_t g, int32_t root, int32_t *level_out, int32_t *parent_out
  *                         at element i * n.  Device pointers if
  *                         opt->out_on_device, else host pointers.
  *   opt                   as for bfs_run, except: rule must be BFS_RULE_EDGES,
- *                         BFS_RULE_TOPDOWN or BFS_RULE_BOTTOMUP; graph_launch
- *                         must be 0; probe_k is not used (the pull scans each
+ *                         BFS_RULE_TOPDOWN or BFS_RULE_BOTTOMUP; with
+ *                         graph_launch each group of up to 64 roots is one
+ *                         hipGraph launch (init, seed, the layers' push and
+ *                         pull kernels, finisher), captured once per group
+ *                         size and option set; probe_k is not used (the pull scans each
  *                         row until every pending root has found a parent).
  *   stats                 may be NULL; not allowed with opt->async.  reached
  *                         and reached_degree_sum are summed over the roots,

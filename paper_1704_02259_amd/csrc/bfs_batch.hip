@@ -98,13 +98,18 @@ static __device__ __forceinline__ void td_discover(const BParams &P, unsigned lo
     }
 }
 
-// Bottom-up layer, rows longer than hub_deg: each 2^hub_log2-entry chunk of
-// such a row (the hub table) is scanned by one wavefront, so a long row is
-// spread over many wavefronts.  Within its chunk a wavefront finds every
-// pending lane's first hit (exclusive OR-scan over the lanes of each 64-entry
-// step) and stops once all pending lanes have one; across chunks the
-// smallest hit wins through an unsigned atomic minimum on the parent.  The
-// chunk's lanes are ORed into next[v]; the pull kernel completes v.
+// Bottom-up layer, rows longer than hub_deg.  Such a row is split into
+// segments of 2^seg_log2 chunks of 2^hub_log2 entries, one wavefront per
+// segment, so a long row is spread over many wavefronts.  A wavefront scans
+// its segment's chunks in ascending order, finding every pending lane's first
+// hit (exclusive OR-scan over the lanes of each 64-entry step), and stops once
+// all pending lanes have one.  Before each chunk it drops the lanes that the
+// row's earlier segments have published as found: their hits are smaller ids,
+// so the canonical parent of such a lane cannot lie in this segment.  (Masks
+// left from earlier layers only hold lanes already visited at v, which are
+// not pending.)  Across segments the smallest hit wins through an unsigned
+// atomic minimum on the parent.  The segment's lanes are ORed into next[v];
+// the pull kernel completes v.
 static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gwave, long long nwaves)
 {
     const int lane = __lane_id();
@@ -113,33 +118,48 @@ static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gw
     unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
     unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
     const long long CH = 1ll << P.hub_log2;
-    for (long long idx = gwave; idx < P.n_hub; idx += nwaves) {
-        const Item it = P.hub[idx];
+    for (long long sidx = gwave; sidx < P.n_hseg; sidx += nwaves) {
+        const Item it = P.hseg[sidx];
         const int v = it.u;
         unsigned long long rem = P.active & ~P.vis[v];
         if (!rem) continue;
-        const long long s = P.off[v] + ((long long)it.chunk << P.hub_log2);
-        const long long e = min(s + CH, P.off[v + 1]);
+        const int sj = it.chunk >> P.seg_log2;             // segment number within the row
+        const long long first = sidx - sj;                  // the row's first segment
+        const long long rs = P.off[v], re = P.off[v + 1];
+        const long long s = rs + ((long long)it.chunk << P.hub_log2);
+        const long long e = min(s + (CH << P.seg_log2), re);
+        const bool publish = e < re;                        // later segments exist
         unsigned long long found = 0;
-        for (long long b = s; b < e && rem; b += 64) {
-            const long long j = b + lane;
-            int u = 0;
-            unsigned long long f = 0;
-            if (j < e) {
-                u = P.col[j];
-                if (test_bit(ufront, u)) f = front[u] & rem;
+        for (long long cb = s; cb < e; cb += CH) {
+            if (sj > 0) {
+                unsigned long long x = 0;
+                for (int t = lane; t < sj; t += 64) x |= ld_relaxed(&P.sfound[first + t]);
+                rem &= ~wave_or_u64(x);
             }
-            if (!__ballot(f != 0)) continue;
-            unsigned long long newb = f & ~wave_excl_or(f);
-            while (newb) {
-                const int bb = __ffsll((long long)newb) - 1;
-                newb &= newb - 1;
-                atomicMin((unsigned *)&P.par[bb][v], (unsigned)u);
-                P.lvl[bb][v] = d + 1;
+            if (!rem) break;
+            const long long ce = min(cb + CH, e);
+            for (long long b = cb; b < ce && rem; b += 64) {
+                const long long j = b + lane;
+                int u = 0;
+                unsigned long long f = 0;
+                if (j < ce) {
+                    u = P.col[j];
+                    if (test_bit(ufront, u)) f = front[u] & rem;
+                }
+                if (!__ballot(f != 0)) continue;
+                unsigned long long newb = f & ~wave_excl_or(f);
+                while (newb) {
+                    const int bb = __ffsll((long long)newb) - 1;
+                    newb &= newb - 1;
+                    atomicMin((unsigned *)&P.par[bb][v], (unsigned)u);
+                    P.lvl[bb][v] = d + 1;
+                }
+                const unsigned long long all = wave_or_u64(f);
+                rem &= ~all;
+                found |= all;
             }
-            const unsigned long long all = wave_or_u64(f);
-            rem &= ~all;
-            found |= all;
+            if (publish && found && lane == 0)
+                __hip_atomic_store(&P.sfound[sidx], found, __ATOMIC_RELAXED, AGENT);
         }
         if (found && lane == 0) {
             const unsigned long long old = atomicOr(&next[v], found);
@@ -598,6 +618,7 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P, LaneP
         P.ubm[P.W + w] = 0ull;
         P.ubm[2 * P.W + w] = 0ull;
     }
+    for (long long i = gt; i < P.n_hseg; i += nt) P.sfound[i] = 0ull;
     if (gt < kLanes) {
         const_cast<int **>(P.lvl)[gt] = gt < P.k ? out.level[gt] : nullptr;
         const_cast<int **>(P.par)[gt] = gt < P.k ? out.parent[gt] : nullptr;
@@ -746,6 +767,17 @@ hipError_t launch_batch_finish(const BParams &p, hipStream_t s)
 {
     hipLaunchKernelGGL(bfs_batch_finish_kernel, dim3(1), dim3(kFinishBlock), 0, s, p);
     return hipGetLastError();
+}
+
+void *kernel_ptr_batch(int which)
+{
+    switch (which) {
+    case BK_INIT: return (void *)bfs_batch_init_kernel;
+    case BK_SEED: return (void *)bfs_batch_seed_kernel;
+    case BK_PUSH: return (void *)bfs_batch_push_kernel;
+    case BK_PULL: return (void *)bfs_batch_pull_kernel;
+    default: return (void *)bfs_batch_finish_kernel;
+    }
 }
 
 int batch_blocks_per_cu()

@@ -263,6 +263,13 @@ struct BParams {
     long long n_hub;
     int hub_log2;
     int hub_deg;
+    // bottom-up scans of hub rows: segments of 2^seg_log2 consecutive chunks,
+    // one item (row, first chunk) each, the row's segments contiguous; sfound
+    // holds per segment the lanes it has found (cleared per batch)
+    const Item *hseg;
+    long long n_hseg;
+    unsigned long long *sfound;
+    int seg_log2;
     int k;                               // lanes in use (1..64)
     int rule;
     unsigned long long active;           // bit b set for b < k
@@ -321,6 +328,9 @@ void *kernel_ptr_init_root();
 void *kernel_ptr_bin_scan();
 void *kernel_ptr_bin_scatter();
 void *kernel_ptr_bin_reduce();
+// The batched kernels, for graph nodes (arguments as their launchers pass them).
+enum { BK_INIT, BK_SEED, BK_PUSH, BK_PULL, BK_FINISH };
+void *kernel_ptr_batch(int which);
 constexpr int kReduceBlockThreads = 512;   // threads of a binned reduce block
 int layer_blocks_per_cu(bool wide);
 

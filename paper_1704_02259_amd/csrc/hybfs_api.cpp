@@ -762,6 +762,11 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
             }
         g->n_hub = (long long)hub.size();
     }
+    // the same rows in segments of 2^kSegLog2 chunks (batched bottom-up scans)
+    std::vector<Item> hseg;
+    for (size_t i = 0; i < hub.size(); ++i)
+        if ((hub[i].chunk & ((1 << kSegLog2) - 1)) == 0) hseg.push_back(hub[i]);
+    g->n_hseg = (long long)hseg.size();
 
     if ((e = hipMalloc(&g->d_off, (n + 1) * 8)) != hipSuccess) return hip_fail(e, "graph offsets");
     if ((e = hipMalloc(&g->d_col, std::max<int64_t>(nnz, 1) * 4)) != hipSuccess) return hip_fail(e, "graph columns");
@@ -773,6 +778,11 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     if (!hub.empty() &&
         (e = hipMemcpy(g->d_hub, hub.data(), hub.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "upload hub table");
+    if ((e = hipMalloc(&g->d_hseg, std::max<size_t>(hseg.size(), 1) * sizeof(Item))) != hipSuccess)
+        return hip_fail(e, "hub segment table");
+    if (!hseg.empty() &&
+        (e = hipMemcpy(g->d_hseg, hseg.data(), hseg.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "upload hub segment table");
     e = hipMemcpy(g->d_off, h_off, (n + 1) * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload offsets");
     if (nnz > 0) {
@@ -835,6 +845,7 @@ int bfs_graph_destroy(bfs_graph_t gh)
     if (g->d_deg) hipFree(g->d_deg);
     if (g->d_slab) hipFree(g->d_slab);
     if (g->d_hub) hipFree(g->d_hub);
+    if (g->d_hseg) hipFree(g->d_hseg);
     delete g;
     return BFS_OK;
 }
@@ -850,7 +861,7 @@ int bfs_graph_info_get(bfs_graph_t gh, bfs_graph_info *info)
     info->isolated = g->isolated;
     info->max_degree = g->max_degree;
     info->device_bytes = (g->n + 1) * 8 + g->nnz * 4 + g->W * 8 + g->n * 4 * (1 + g->slab_k) +
-                         g->n_hub * (int64_t)sizeof(Item);
+                         (g->n_hub + g->n_hseg) * (int64_t)sizeof(Item);
     info->workspace_bytes = (int64_t)workspace_bytes(g->W);
     info->grid_blocks = g->grid_default;
     info->block_threads = kBlock;
@@ -859,7 +870,7 @@ int bfs_graph_info_get(bfs_graph_t gh, bfs_graph_info *info)
     info->hub_degree = g->hub_deg;
     info->hub_chunks = g->n_hub;
     info->typical_layers = g->depth.typical.load();
-    info->batch_workspace_bytes = (int64_t)batch_workspace_bytes(g->n, g->W);
+    info->batch_workspace_bytes = (int64_t)batch_workspace_bytes(g);
     info->layer_kernel_wide = g->wide ? 1 : 0;
     info->reserved = 0;
     return BFS_OK;

@@ -1,5 +1,6 @@
 // Host side of the batched multi-source traversal (bfs_run_batch).
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 
 #include "hybfs_internal.h"
@@ -15,15 +16,20 @@ BatchWorkspace::~BatchWorkspace()
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     for (hipEvent_t e : layer_ev) hipEventDestroy(e);
+    for (auto &kv : replays) {
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+    }
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t batch_workspace_bytes(long long n, long long W)
+size_t batch_workspace_bytes(const Graph *g)
 {
+    const long long n = g->n, W = g->W;
     return align256((size_t)n * 8) + align256((size_t)n * 8 * 3) + align256((size_t)W * 8 * 3) +
-           align256(sizeof(BCtrl)) + align256((size_t)kTraceCap * sizeof(LayerRec)) +
-           align256(2 * kLanes * sizeof(int *));
+           align256((size_t)std::max<long long>(g->n_hseg, 1) * 8) + align256(sizeof(BCtrl)) +
+           align256((size_t)kTraceCap * sizeof(LayerRec)) + align256(2 * kLanes * sizeof(int *));
 }
 
 int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
@@ -46,13 +52,14 @@ int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
         (e = hipEventCreateWithFlags(&w->e1, hipEventDisableSystemFence)) != hipSuccess)
         return hip_fail(e, "event");
     const long long n = g->n, W = g->W;
-    w->bytes = batch_workspace_bytes(n, W);
+    w->bytes = batch_workspace_bytes(g);
     if ((e = hipMalloc(&w->dbuf, w->bytes)) != hipSuccess) return hip_fail(e, "batch workspace allocation");
     char *b = (char *)w->dbuf;
     size_t o = 0;
     w->vis = (unsigned long long *)(b + o);  o += align256((size_t)n * 8);
     w->fm = (unsigned long long *)(b + o);   o += align256((size_t)n * 8 * 3);
     w->ubm = (unsigned long long *)(b + o);  o += align256((size_t)W * 8 * 3);
+    w->sfound = (unsigned long long *)(b + o);  o += align256((size_t)std::max<long long>(g->n_hseg, 1) * 8);
     w->ctrl = (BCtrl *)(b + o);              o += align256(sizeof(BCtrl));
     w->trace = (LayerRec *)(b + o);          o += align256((size_t)kTraceCap * sizeof(LayerRec));
     w->tab = (int **)(b + o);
@@ -78,6 +85,10 @@ static void fill_batch_params(const Graph *g, const BatchWorkspace *w, const bfs
     P->n_hub = g->n_hub;
     P->hub_log2 = kChunkLog2;
     P->hub_deg = g->hub_deg;
+    P->hseg = g->d_hseg;
+    P->n_hseg = g->n_hseg;
+    P->sfound = w->sfound;
+    P->seg_log2 = kSegLog2;
     P->k = k;
     P->rule = opt.rule;
     P->active = k >= 64 ? ~0ull : ((1ull << k) - 1ull);
@@ -96,6 +107,14 @@ static void fill_batch_params(const Graph *g, const BatchWorkspace *w, const bfs
     P->async_run = opt.async;
 }
 
+static void fill_roots(const Graph *g, const int32_t *roots, int k, RootSet *R, BParams *P)
+{
+    for (int i = 0; i < kLanes; ++i) {
+        R->r[i] = i < k ? roots[i] : -1;
+        if (i < k && roots[i] == g->fail_root) P->fail_injected = 1;
+    }
+}
+
 // [init, seed, L x (push, pull), finisher] for one group of at most 64 roots.
 int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
                   const LanePtrs &out, hipStream_t s, bool profile, int *layers_enqueued)
@@ -103,10 +122,7 @@ int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int
     BParams P;
     fill_batch_params(g, w, opt, k, &P);
     RootSet R;
-    for (int i = 0; i < kLanes; ++i) {
-        R.r[i] = i < k ? roots[i] : -1;
-        if (i < k && roots[i] == g->fail_root) P.fail_injected = 1;
-    }
+    fill_roots(g, roots, k, &R, &P);
     const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_grid;
     const int pgrid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_pull_grid;
     const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->batch_depth.typical.load();
@@ -132,6 +148,85 @@ int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int
     return BFS_OK;
 }
 
+int enqueue_batch_graph(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
+                        const LanePtrs &out, hipStream_t s, int *layers_enqueued)
+{
+    BParams P;
+    fill_batch_params(g, w, opt, k, &P);
+    RootSet R;
+    fill_roots(g, roots, k, &R, &P);
+    const int grid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_grid;
+    const int pgrid = opt.grid_blocks > 0 ? opt.grid_blocks : g->batch_pull_grid;
+    const int L = opt.layers_per_launch > 0 ? opt.layers_per_launch : g->batch_depth.typical.load();
+    char key[160];
+    snprintf(key, sizeof key, "%d/%d/%lld/%lld/%d/%d/%d/%d", k, opt.rule, P.alpha, P.beta, P.wpg, grid, pgrid, L);
+    hipError_t e;
+    auto it = w->replays.find(key);
+    if (it == w->replays.end()) {
+        BatchWorkspace::Replay Q;
+        Q.grid = grid;
+        Q.layers = L;
+        // the node arguments are copied when a node is added
+        std::vector<int> layer_idx(L);
+        for (int i = 0; i < L; ++i) layer_idx[i] = i;
+        if ((e = hipGraphCreate(&Q.graph, 0)) != hipSuccess) return hip_fail(e, "graph create");
+        hipGraphNode_t prev = nullptr;
+        auto add = [&](int which, dim3 gd, dim3 bd, void **args, hipGraphNode_t *keep) -> hipError_t {
+            hipKernelNodeParams np;
+            std::memset(&np, 0, sizeof np);
+            np.func = kernel_ptr_batch(which);
+            np.gridDim = gd;
+            np.blockDim = bd;
+            np.kernelParams = args;
+            hipGraphNode_t node;
+            const hipError_t r = hipGraphAddKernelNode(&node, Q.graph, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+            if (r == hipSuccess) {
+                prev = node;
+                if (keep) *keep = node;
+            }
+            return r;
+        };
+        LanePtrs o = out;
+        void *init_args[] = {&P, &o};
+        void *seed_args[] = {&P, &R};
+        void *fin_args[] = {&P};
+        if ((e = add(BK_INIT, dim3(grid, k + 1), dim3(kBlock), init_args, &Q.init)) != hipSuccess ||
+            (e = add(BK_SEED, dim3(1), dim3(64), seed_args, &Q.seed)) != hipSuccess)
+            return hip_fail(e, "graph batch nodes");
+        for (int i = 0; i < L; ++i) {
+            void *args[] = {&P, &layer_idx[i]};
+            if ((e = add(BK_PUSH, dim3(grid), dim3(kBlock), args, nullptr)) != hipSuccess ||
+                (e = add(BK_PULL, dim3(pgrid), dim3(kPullWaves * 64), args, nullptr)) != hipSuccess)
+                return hip_fail(e, "graph batch layer nodes");
+        }
+        if ((e = add(BK_FINISH, dim3(1), dim3(kFinishBlock), fin_args, nullptr)) != hipSuccess)
+            return hip_fail(e, "graph batch finisher node");
+        if ((e = hipGraphInstantiate(&Q.exec, Q.graph, nullptr, nullptr, 0)) != hipSuccess)
+            return hip_fail(e, "graph instantiate");
+        it = w->replays.emplace(key, Q).first;
+    }
+    BatchWorkspace::Replay &Q = it->second;
+    // the run's outputs, flags and roots into the two nodes that read them
+    LanePtrs o = out;
+    void *init_args[] = {&P, &o};
+    void *seed_args[] = {&P, &R};
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.func = kernel_ptr_batch(BK_INIT);
+    kp.gridDim = dim3(Q.grid, k + 1);
+    kp.blockDim = dim3(kBlock);
+    kp.kernelParams = init_args;
+    if ((e = hipGraphExecKernelNodeSetParams(Q.exec, Q.init, &kp)) != hipSuccess) return hip_fail(e, "graph update");
+    kp.func = kernel_ptr_batch(BK_SEED);
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.kernelParams = seed_args;
+    if ((e = hipGraphExecKernelNodeSetParams(Q.exec, Q.seed, &kp)) != hipSuccess) return hip_fail(e, "graph update");
+    if ((e = hipGraphLaunch(Q.exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+    *layers_enqueued = Q.layers;
+    return BFS_OK;
+}
+
 }  // namespace hybfs
 
 using namespace hybfs;
@@ -151,7 +246,6 @@ int bfs_run_batch(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t *leve
     if (rc) return rc;
     if (opt.rule == BFS_RULE_TABLE)
         return set_error(BFS_E_INVALID, "batched runs take the edge rule or a forced direction");
-    if (opt.graph_launch) return set_error(BFS_E_INVALID, "batched runs do not replay graphs");
     if (k < 1) return set_error(BFS_E_INVALID, "k = %d roots; need at least one", k);
     if (!roots) return set_error(BFS_E_INVALID, "NULL roots");
     for (int i = 0; i < k; ++i)
@@ -206,7 +300,8 @@ int bfs_run_batch(bfs_graph_t gh, const int32_t *roots, int32_t k, int32_t *leve
             out.level[b] = b < kg ? lvl + (long long)b * n : nullptr;
             out.parent[b] = b < kg ? par + (long long)b * n : nullptr;
         }
-        rc = enqueue_batch(g, w, opt, roots + g0, kg, out, s, profile, &launched);
+        if (opt.graph_launch && !profile) rc = enqueue_batch_graph(g, w, opt, roots + g0, kg, out, s, &launched);
+        else rc = enqueue_batch(g, w, opt, roots + g0, kg, out, s, profile, &launched);
         if (rc) return rc;
         if (stats && (e = hipEventRecord(w->e1, s)) != hipSuccess) return hip_fail(e, "event record");
         if (opt.async) continue;

@@ -17,6 +17,7 @@ namespace hybfs {
 
 constexpr int kTraceCap = 4096;      // per-layer trace records kept on the device
 constexpr int kChunkLog2 = 8;        // top-down hub chunks cover 256 edges
+constexpr int kSegLog2 = 3;          // batched bottom-up: hub rows in segments of 8 chunks
 constexpr int kHubDegree = 256;      // above this degree, rows are split into hub-table chunks
 // Default layer-kernel blocks per CU (fewer where the occupancy query allows
 // fewer): five 256-thread blocks keep more dependent probe chains in flight
@@ -87,6 +88,7 @@ struct BatchWorkspace {
     unsigned long long *vis = nullptr;   // [n]
     unsigned long long *fm = nullptr;    // [3n]
     unsigned long long *ubm = nullptr;   // [3W]
+    unsigned long long *sfound = nullptr;  // [n_hseg] lanes each hub-row segment found
     BCtrl *ctrl = nullptr;
     LayerRec *trace = nullptr;
     int **tab = nullptr;                 // device [2 * kLanes]: per-lane level, then parent arrays
@@ -96,6 +98,16 @@ struct BatchWorkspace {
     LayerRec *h_trace = nullptr;         // pinned
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> layer_ev;
+    // captured launch sequences of one group: key = lanes, option set and
+    // layer count; a run rewrites the init node (output table, run flags)
+    // and the seed node (roots)
+    struct Replay {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t init = nullptr, seed = nullptr;
+        int grid = 0, layers = 0;
+    };
+    std::map<std::string, Replay> replays;
     size_t held() const { return (dbuf ? bytes : 0) + (out_tmp ? (size_t)out_tmp_elems * 4 : 0); }
     ~BatchWorkspace();
 };
@@ -124,6 +136,8 @@ struct Graph {
     int slab_k = 0;
     Item *d_hub = nullptr;        // top-down chunks of vertices above hub_deg
     long long n_hub = 0;
+    Item *d_hseg = nullptr;       // batched bottom-up: segments of kSegLog2 chunks of those rows
+    long long n_hseg = 0;
     int hub_deg = 0;
     long long isolated = 0, max_degree = 0;
     std::vector<int32_t> h_deg;   // host copy of the degrees (launch choices)
@@ -161,7 +175,7 @@ size_t queue_bytes(const Graph *g, bool queues, bool hub_lists);
 // (the stream must be synchronized): BFS_E_DEVICE with a message, and the
 // record cleared; BFS_OK when there were none.
 int check_async_errors(Graph *g, void *stream);
-size_t batch_workspace_bytes(long long n, long long W);
+size_t batch_workspace_bytes(const Graph *g);
 // Device bytes the workspaces of g for `stream` hold (single-root and
 // batched, each optionally returned), and their release (the stream must be
 // idle, the workspaces unused); the device bytes the single-root workspace of
@@ -172,6 +186,9 @@ size_t single_run_bytes(Graph *g, void *stream, const bfs_options &opt);
 int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out);
 int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
                   const LanePtrs &out, hipStream_t s, bool profile, int *layers_enqueued);
+// The same sequence as one hipGraph launch (captured on first use).
+int enqueue_batch_graph(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
+                        const LanePtrs &out, hipStream_t s, int *layers_enqueued);
 void fill_params(const Graph *g, const Workspace *w, const bfs_options &opt, Params *P);
 int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, int *lvl, int *par,
                       hipStream_t s, int *layers_enqueued, bool profile, int *layer0_kernel = nullptr);

@@ -130,7 +130,7 @@ long long Server::need(int i, Graph *g, int k, const bfs_options &opt) const
     if (k == 1) {
         after = (long long)single_run_bytes(g, sl.stream, opt) + (long long)batch;
     } else {
-        after = (long long)single + (long long)(batch ? batch : batch_workspace_bytes(g->n, g->W));
+        after = (long long)single + (long long)(batch ? batch : batch_workspace_bytes(g));
         // a smaller staging buffer is freed before the larger one is allocated
         if (!cfg.out_on_device) stage = std::max(stage, 8LL * k * g->n);
     }

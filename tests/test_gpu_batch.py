@@ -179,6 +179,48 @@ def test_batch_async_back_to_back(torch, kron16):
         _check_rows(g, "kron16", roots, lv.cpu().numpy().reshape(-1, g.n), pa.cpu().numpy().reshape(-1, g.n))
 
 
+def test_batch_graph_replay(torch, hyb, kron16):
+    """graph_launch=1: each group of up to 64 roots is one hipGraph launch,
+    captured once per group size and option set.  Replays with other roots,
+    group sizes (17, 64, 130 = three groups), output buffers and layer counts,
+    synchronous with stats, and asynchronous series on one stream (each replay
+    rewrites the init and seed nodes while the previous one may still run),
+    with direct runs and torch work between them; every replay against the
+    oracle."""
+    g, G = kron16
+    sets = [_kron16_roots(g, 64, 41), _kron16_roots(g, 64, 42), _kron16_roots(g, 17, 43),
+            _kron16_roots(g, 130, 44), _kron16_roots(g, 64, 45)]
+    for roots in sets:
+        _say("batch replay", len(roots), int(roots[0]))
+        lv, pa, st = _gpu_batch(torch, G, roots, graph_launch=1)
+        _check_rows(g, "kron16", roots, lv, pa)
+        _check_stats(g, "kron16", roots, st)
+        lv, pa, _ = _gpu_batch(torch, G, roots)          # a direct run between replays
+        _check_rows(g, "kron16", roots, lv, pa)
+    for roots in sets[:2]:
+        lv, pa, st = _gpu_batch(torch, G, roots, graph_launch=1, layers_per_launch=2)
+        _check_rows(g, "kron16", roots, lv, pa)
+        _check_stats(g, "kron16", roots, st)
+    s = torch.cuda.Stream()
+    bufs = []
+    for roots in sets + sets[::-1]:
+        lv = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
+        pa = torch.empty(len(roots) * g.n, dtype=torch.int32, device="cuda")
+        G.run_batch(roots, lv, pa, stream=s.cuda_stream, async_=1, graph_launch=1)
+        bufs.append((roots, lv, pa))
+    s.synchronize()
+    for roots, lv, pa in bufs:
+        _check_rows(g, "kron16", roots, lv.cpu().numpy().reshape(-1, g.n), pa.cpu().numpy().reshape(-1, g.n))
+    for name, gs, roots in _small_cases():
+        roots = np.array(roots, dtype=np.int32)
+        Gs = hyb.Graph.from_csr(gs)
+        for rep in range(2):
+            lv, pa, st = _gpu_batch(torch, Gs, roots, graph_launch=1)
+            _check_rows(gs, name, roots, lv, pa)
+            _check_stats(gs, name, roots, st)
+        Gs.close()
+
+
 def _small_cases():
     yield "path1000", inputs.path_graph(1000), [0, 500, 999, 0, 1]
     yield "cycle257", inputs.cycle_graph(257), [0, 128, 256]
@@ -224,7 +266,7 @@ def test_batch_unsorted_rows(torch, hyb):
 def test_batch_invalid_arguments(torch, kron16):
     from paper_1704_02259_amd import hybfs
     g, G = kron16
-    for roots, kw in (([0, g.n], {}), ([-1], {}), ([0], {"rule": "table"}), ([0], {"graph_launch": 1})):
+    for roots, kw in (([0, g.n], {}), ([-1], {}), ([0], {"rule": "table"})):
         with pytest.raises(hybfs.HybfsError) as ei:
             G.run_batch(roots, **kw)
         assert ei.value.code == hybfs.BFS_E_INVALID
