@@ -100,7 +100,10 @@ static __device__ __forceinline__ void td_discover(const BParams &P, unsigned lo
 
 // Bottom-up layer, rows longer than hub_deg.  Such a row is split into
 // segments of 2^seg_log2 chunks of 2^hub_log2 entries, one wavefront per
-// segment, so a long row is spread over many wavefronts.  A wavefront scans
+// segment, so a long row is spread over many wavefronts; the segments are
+// taken in the order of their number within the row (all rows' first
+// segments, then the second ones, ...), so a row's earlier segments have
+// mostly finished when its later ones start.  A wavefront scans
 // its segment's chunks in ascending order, finding every pending lane's first
 // hit (exclusive OR-scan over the lanes of each 64-entry step), and stops once
 // all pending lanes have one.  Before each chunk it drops the lanes that the
@@ -118,15 +121,16 @@ static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gw
     unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
     unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
     const long long CH = 1ll << P.hub_log2;
-    for (long long sidx = gwave; sidx < P.n_hseg; sidx += nwaves) {
-        const Item it = P.hseg[sidx];
-        const int v = it.u;
+    for (long long idx = gwave; idx < P.n_hseg; idx += nwaves) {
+        const HSeg it = P.hseg[idx];
+        const int v = it.v;
         unsigned long long rem = P.active & ~P.vis[v];
         if (!rem) continue;
-        const int sj = it.chunk >> P.seg_log2;             // segment number within the row
-        const long long first = sidx - sj;                  // the row's first segment
+        const int sj = it.seg;                              // segment number within the row
+        const long long first = it.first;                   // found mask of the row's segment 0
+        const long long sidx = first + sj;
         const long long rs = P.off[v], re = P.off[v + 1];
-        const long long s = rs + ((long long)it.chunk << P.hub_log2);
+        const long long s = rs + ((long long)sj << (P.hub_log2 + P.seg_log2));
         const long long e = min(s + (CH << P.seg_log2), re);
         const bool publish = e < re;                        // later segments exist
         unsigned long long found = 0;

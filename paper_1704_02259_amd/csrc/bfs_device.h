@@ -89,6 +89,15 @@ struct Item {
     int chunk;
 };
 
+// A segment of a hub row for the batched bottom-up scan: row v, segment
+// number seg within the row, and `first`, the index of the row's segment 0
+// in the row-major numbering that indexes the found masks.
+struct HSeg {
+    int v;
+    int seg;
+    long long first;
+};
+
 struct Params {
     long long n, nnz, W;                 // vertices, stored entries, bitmap words
     const long long *off;                // int64 [n+1]
@@ -264,9 +273,10 @@ struct BParams {
     int hub_log2;
     int hub_deg;
     // bottom-up scans of hub rows: segments of 2^seg_log2 consecutive chunks,
-    // one item (row, first chunk) each, the row's segments contiguous; sfound
-    // holds per segment the lanes it has found (cleared per batch)
-    const Item *hseg;
+    // listed by segment number (every row's segment 0, then segment 1, ...);
+    // sfound holds per segment, numbered row-major, the lanes it has found
+    // (cleared per batch)
+    const HSeg *hseg;
     long long n_hseg;
     unsigned long long *sfound;
     int seg_log2;

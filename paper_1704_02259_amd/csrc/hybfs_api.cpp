@@ -762,10 +762,21 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
             }
         g->n_hub = (long long)hub.size();
     }
-    // the same rows in segments of 2^kSegLog2 chunks (batched bottom-up scans)
-    std::vector<Item> hseg;
-    for (size_t i = 0; i < hub.size(); ++i)
-        if ((hub[i].chunk & ((1 << kSegLog2) - 1)) == 0) hseg.push_back(hub[i]);
+    // the same rows in segments of 2^kSegLog2 chunks (batched bottom-up
+    // scans), numbered row-major, listed by segment number so that a row's
+    // earlier segments are scanned (and publish their finds) first
+    std::vector<HSeg> hseg;
+    {
+        long long id = 0, first = 0;
+        for (size_t i = 0; i < hub.size(); ++i) {
+            if (hub[i].chunk == 0) first = id;
+            if ((hub[i].chunk & ((1 << kSegLog2) - 1)) == 0) {
+                hseg.push_back(HSeg{hub[i].u, hub[i].chunk >> kSegLog2, first});
+                ++id;
+            }
+        }
+        std::stable_sort(hseg.begin(), hseg.end(), [](const HSeg &a, const HSeg &b) { return a.seg < b.seg; });
+    }
     g->n_hseg = (long long)hseg.size();
 
     if ((e = hipMalloc(&g->d_off, (n + 1) * 8)) != hipSuccess) return hip_fail(e, "graph offsets");
@@ -778,10 +789,10 @@ int bfs_graph_create(int64_t n, int64_t nnz, const int64_t *row_offsets, const i
     if (!hub.empty() &&
         (e = hipMemcpy(g->d_hub, hub.data(), hub.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "upload hub table");
-    if ((e = hipMalloc(&g->d_hseg, std::max<size_t>(hseg.size(), 1) * sizeof(Item))) != hipSuccess)
+    if ((e = hipMalloc(&g->d_hseg, std::max<size_t>(hseg.size(), 1) * sizeof(HSeg))) != hipSuccess)
         return hip_fail(e, "hub segment table");
     if (!hseg.empty() &&
-        (e = hipMemcpy(g->d_hseg, hseg.data(), hseg.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)
+        (e = hipMemcpy(g->d_hseg, hseg.data(), hseg.size() * sizeof(HSeg), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "upload hub segment table");
     e = hipMemcpy(g->d_off, h_off, (n + 1) * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload offsets");
@@ -861,7 +872,7 @@ int bfs_graph_info_get(bfs_graph_t gh, bfs_graph_info *info)
     info->isolated = g->isolated;
     info->max_degree = g->max_degree;
     info->device_bytes = (g->n + 1) * 8 + g->nnz * 4 + g->W * 8 + g->n * 4 * (1 + g->slab_k) +
-                         (g->n_hub + g->n_hseg) * (int64_t)sizeof(Item);
+                         g->n_hub * (int64_t)sizeof(Item) + g->n_hseg * (int64_t)sizeof(HSeg);
     info->workspace_bytes = (int64_t)workspace_bytes(g->W);
     info->grid_blocks = g->grid_default;
     info->block_threads = kBlock;

@@ -136,7 +136,7 @@ struct Graph {
     int slab_k = 0;
     Item *d_hub = nullptr;        // top-down chunks of vertices above hub_deg
     long long n_hub = 0;
-    Item *d_hseg = nullptr;       // batched bottom-up: segments of kSegLog2 chunks of those rows
+    HSeg *d_hseg = nullptr;       // batched bottom-up: segments of 2^kSegLog2 chunks of those rows
     long long n_hseg = 0;
     int hub_deg = 0;
     long long isolated = 0, max_degree = 0;
