@@ -418,6 +418,70 @@ def layer_profile(torch, hybfs, dev, workload, nroots, kw, out_path):
     return out
 
 
+def batch_profile(torch, hybfs, dev, workload, nbatches, out_path, k=64):
+    """Per-layer profile of the batched traversal of the workload's first k
+    roots: nbatches plain batches (direct launches, the dispatches a
+    rocprofv3 run of this command attributes to layers in launch order), then
+    one batch with per-layer HIP events.  Writes the map join_batch_counters
+    reads."""
+    import inputs
+    g = inputs.workload_graph(workload)
+    roots = inputs.workload_roots(workload, g, k).astype(np.int32)
+    G = hybfs.Graph.from_csr(g, flags=hybfs.BFS_GRAPH_ASSUME_VALID)
+    blv = torch.empty((k, g.n), dtype=torch.int32, device=dev)
+    bpa = torch.empty((k, g.n), dtype=torch.int32, device=dev)
+    runs = []
+    for _ in range(nbatches):
+        _, _, st = G.run_batch(roots, blv, bpa, stats=True)
+        runs.append({"layer_launches": st["layer_launches"], "num_layers": st["num_layers"],
+                     "device_us": round(st["device_us"], 1)})
+    _, _, st = G.run_batch(roots, blv, bpa, stats=True, profile_layers=1)
+    layers = [{"layer": d, "dir": "BU" if x["dir"] else "TD", "n_f": x["n_f"], "m_f": x["m_f"],
+               "us": round(x["kernel_us"], 1)} for d, x in enumerate(st["layers"])]
+    out = {"workload": workload, "k": k, "n": g.n, "nnz": g.nnz, "batches": runs, "layers": layers,
+           "profiled_device_us": round(st["device_us"], 1)}
+    with open(out_path, "w") as f:
+        json.dump(out, f)
+    G.close()
+    return out
+
+
+def join_batch_counters(map_path, csv_paths, fetch_factor=2.0, write_factor=1.0):
+    """Per-dispatch durations (a rocprofv3 --kernel-trace CSV) and counters
+    (--pmc CSVs) of the last plain batch batch_profile ran, by launch order:
+    a batch starts at its init kernel, then the seed kernel, then one push and
+    one pull kernel per enqueued layer, then the finisher."""
+    import csv
+    with open(map_path) as f:
+        bm = json.load(f)
+    disp = {}
+    for p in csv_paths:
+        with open(p) as f:
+            for r in csv.DictReader(f):
+                if "bfs_batch" not in r["Kernel_Name"]:
+                    continue
+                ent = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"].split("(")[0].split("::")[-1]})
+                if "Counter_Name" in r:
+                    ent[r["Counter_Name"]] = ent.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                else:
+                    ent["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    groups = []
+    for did in sorted(disp):
+        if disp[did]["name"] == "bfs_batch_init_kernel":
+            groups.append([])
+        if groups:
+            groups[-1].append(disp[did])
+    seq = groups[len(bm["batches"]) - 1]
+    rows = []
+    for e in seq:
+        h, m = e.get("TCC_HIT_sum"), e.get("TCC_MISS_sum")
+        rows.append({"kernel": e["name"], "us": e["ns"] / 1e3 if "ns" in e else None,
+                     "fetch_bytes": e["FETCH_SIZE"] * 1024 * fetch_factor if "FETCH_SIZE" in e else None,
+                     "write_bytes": e["WRITE_SIZE"] * 1024 * write_factor if "WRITE_SIZE" in e else None,
+                     "l2_hit": round(h / (h + m), 3) if h is not None and m is not None and h + m else None})
+    return bm, rows
+
+
 def _read_counter_csv(path):
     """Per-dispatch counter values of a rocprofv3 --pmc CSV: {dispatch id:
     (kernel name, {counter: value})}."""
@@ -803,10 +867,35 @@ def main():
     ap.add_argument("--layer-profile", type=int, default=0,
                     help="only the per-layer profile of this many roots of --workload (writes --layer-map)")
     ap.add_argument("--layer-map", default="gpurun_out/layer_map.json")
+    ap.add_argument("--batch-profile", type=int, default=0,
+                    help="N plain batches of the 64 workload roots, then one with per-layer events")
+    ap.add_argument("--batch-workload", default="kron22")
+    ap.add_argument("--batch-map", default="gpurun_out/batch_map.json")
+    ap.add_argument("--join-batch-counters", nargs="*", default=None,
+                    help="kernel-trace / counter CSVs of a --batch-profile run: per-dispatch table")
     ap.add_argument("--join-counters", nargs="*", default=None,
                     help="host only: join rocprofv3 --pmc CSVs with --layer-map; prints a markdown table")
     args = ap.parse_args()
 
+    if args.join_batch_counters is not None:
+        bm, rows = join_batch_counters(args.batch_map, args.join_batch_counters)
+        print(f"{bm['workload']}, {bm['k']} roots, dispatches of the last plain batch")
+        print("| dispatch | layer | dir | n_f | m_f | µs (trace) | HBM read | HBM write | L2 hit |")
+        print("|---|---|---|---|---|---|---|---|---|")
+        li = 0
+        for i, r in enumerate(rows):
+            kind = r["kernel"].replace("bfs_batch_", "").replace("_kernel", "")
+            lay = ""
+            if kind in ("push", "pull"):
+                lay = li
+                if kind == "pull":
+                    li += 1
+            L = bm["layers"][lay] if lay != "" and lay < len(bm["layers"]) else None
+            f = lambda x, u: "" if x is None else f"{x / u:.1f}"
+            print(f"| {kind} | {lay} | {L['dir'] if L else ''} | {L['n_f'] if L else ''} | {L['m_f'] if L else ''} | "
+                  f"{f(r['us'], 1)} | {f(r['fetch_bytes'], 1e6)} MB | {f(r['write_bytes'], 1e6)} MB | "
+                  f"{'' if r['l2_hit'] is None else r['l2_hit']} |")
+        return
     if args.join_counters is not None:
         lm = join_layer_counters(args.layer_map, args.join_counters)
         print(f"{lm['workload']}, options {lm['options']}, layer kernel {lm['layer_kernel']}")
@@ -855,6 +944,11 @@ def main():
     if args.sweep:
         print(json.dumps({"sweep": sweep(torch, hybfs, dev), "unit": "harmonic-mean GTEPS",
                           "data": "synthetic"}), flush=True)
+        return
+    if args.batch_profile:
+        out = batch_profile(torch, hybfs, dev, args.batch_workload, args.batch_profile, args.batch_map)
+        print(json.dumps({"batch_profile": args.batch_workload, "batches": args.batch_profile,
+                          "layers": out["layers"], "map": args.batch_map}))
         return
     if args.layer_profile:
         kw = {}

@@ -98,3 +98,37 @@ def test_join_layer_counters_attributes_dispatches_by_launch_order(tmp_path):
     assert r1["layers"][0]["fetch_bytes"] == 9 * 1024 * 2.0
     assert r1["layers"][1]["fetch_bytes"] == 10 * 1024 * 2.0
     assert r0["layers"][1]["l2_hit"] == 0.75
+
+
+def test_join_batch_counters_takes_the_last_plain_batch(tmp_path):
+    """Two plain batches and a profiled one: the dispatches of the second
+    (init, seed, push/pull per layer, finisher) are returned in launch order,
+    with durations from a kernel trace and counters from a --pmc run; other
+    kernels are ignored."""
+    bm = {"workload": "w", "k": 64, "batches": [{"layer_launches": 4}, {"layer_launches": 4}],
+          "layers": [{"layer": 0, "dir": "TD", "n_f": 1, "m_f": 1, "us": 1.0},
+                     {"layer": 1, "dir": "BU", "n_f": 2, "m_f": 2, "us": 1.0}]}
+    mp = tmp_path / "bmap.json"
+    mp.write_text(json.dumps(bm))
+    one = ["hybfs::bfs_batch_init_kernel(hybfs::BParams, hybfs::LanePtrs)",
+           "hybfs::bfs_batch_seed_kernel(hybfs::BParams, hybfs::RootSet)",
+           "hybfs::bfs_batch_push_kernel(hybfs::BParams, int)", "hybfs::bfs_batch_pull_kernel(hybfs::BParams, int)",
+           "hybfs::bfs_batch_push_kernel(hybfs::BParams, int)", "hybfs::bfs_batch_pull_kernel(hybfs::BParams, int)",
+           "hybfs::bfs_batch_finish_kernel(hybfs::BParams)"]
+    seq = ["__amd_rocclr_fillBufferAligned"] + one + one + one
+    tl = ["Dispatch_Id,Kernel_Name,Start_Timestamp,End_Timestamp"]
+    cl = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    for i, name in enumerate(seq):
+        tl.append(f'{i + 1},"{name}",{1000 * i},{1000 * i + 500 + i}')
+        cl.append(f'{i + 1},"{name}",FETCH_SIZE,{i + 1}')
+        cl.append(f'{i + 1},"{name}",TCC_HIT_sum,1')
+        cl.append(f'{i + 1},"{name}",TCC_MISS_sum,3')
+    tp, cp = tmp_path / "k.csv", tmp_path / "f.csv"
+    tp.write_text("\n".join(tl) + "\n")
+    cp.write_text("\n".join(cl) + "\n")
+    bm2, rows = bench.join_batch_counters(str(mp), [str(tp), str(cp)], fetch_factor=2.0)
+    assert [r["kernel"] for r in rows] == [n.split("(")[0].split("::")[-1] for n in one]
+    # the second batch's dispatches are seq[8..14], ids 9..15
+    assert rows[0]["fetch_bytes"] == 9 * 1024 * 2.0 and rows[-1]["fetch_bytes"] == 15 * 1024 * 2.0
+    assert rows[2]["us"] == (500 + 10) / 1e3
+    assert rows[3]["l2_hit"] == 0.25 and rows[3]["write_bytes"] is None
