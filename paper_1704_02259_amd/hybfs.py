@@ -104,6 +104,18 @@ class HybfsError(RuntimeError):
 _lib = None
 
 
+def _torch_runtime_first():
+    """PyTorch ships its own HIP runtime libraries.  A process that starts the
+    library's HIP runtime before torch's finds torch without a GPU afterwards,
+    so when torch is importable its GPU runtime is started first (the order
+    every caller that allocates through torch uses anyway)."""
+    try:
+        import torch
+    except ImportError:
+        return
+    torch.cuda.is_available()
+
+
 def load():
     """Load libhybfs.so.  Raises ImportError if it has not been built."""
     global _lib
@@ -111,6 +123,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    _torch_runtime_first()
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                               ctypes.c_uint64)

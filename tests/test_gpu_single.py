@@ -480,3 +480,32 @@ def test_graph_replay_fused_init_and_binned_nodes(torch, kron16, hyb):
             a = _gpu_bfs(torch, G, r, graph_launch=1, td_binned=tb)
             _check_against_oracle(g, r, a[0], a[1], a[2])
             assert a[2]["layer0_kernel"] == (2 if deg[r] <= 4096 else 0)
+
+
+def test_library_first_then_torch():
+    """A fresh process that loads the library and runs a traversal before it
+    touches torch still finds torch's GPU afterwards, and both agree (torch's
+    runtime starts first inside load())."""
+    import subprocess
+    code = (
+        "import numpy as np, inputs, oracle\n"
+        "from paper_1704_02259_amd import hybfs\n"
+        "hybfs.load()\n"
+        "g = inputs.kronecker(10)\n"
+        "G = hybfs.Graph.from_csr(g)\n"
+        "r = int(inputs.pick_roots(g, 1, 7)[0])\n"
+        "lv, pa = G.run(r)[:2]\n"
+        "import torch\n"
+        "assert torch.cuda.is_available(), 'torch lost the GPU'\n"
+        "l2 = torch.empty(g.n, dtype=torch.int32, device='cuda')\n"
+        "p2 = torch.empty(g.n, dtype=torch.int32, device='cuda')\n"
+        "G.run(r, l2, p2)\n"
+        "torch.cuda.synchronize()\n"
+        "elv, epa = oracle.bfs(g, r)\n"
+        "assert np.array_equal(lv, elv) and np.array_equal(pa, epa)\n"
+        "assert np.array_equal(l2.cpu().numpy(), elv) and np.array_equal(p2.cpu().numpy(), epa)\n"
+        "print('ok')\n")
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
+    assert out.returncode == 0 and out.stdout.strip().endswith("ok"), out.stdout[-2000:] + out.stderr[-2000:]
