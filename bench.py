@@ -84,6 +84,11 @@ class TimingEvent:
             pass
 
 
+# tuned options of the bench's graphs on MI355X (bfs_tune_table_* format),
+# written by `bench.py --retune --write-tune-table`
+TUNE_TABLE = os.path.join(ROOT, "paper_1704_02259_amd", "tune_table_mi355x.jsonl")
+
+
 def kernel_source_hash() -> str:
     """Hash of the code the layer kernel is built from, with comments and
     whitespace removed, so that only a change of code marks the committed
@@ -112,7 +117,7 @@ def measured_traffic(workload: str):
     return t.get("bytes_per_launch")
 
 
-def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
+def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3, table=None, write_table=None):
     """Batched multi-source traversal against single-root runs on the same
     roots: speedup = sum of single-root times / batch time, outputs equal."""
     import inputs
@@ -128,7 +133,8 @@ def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
     ev = TimingEvent
     # both sides tuned on the same other roots
     troots = inputs.pick_roots(g, k, inputs.ROOT_SEED[int(workload[4:])] + 500)
-    sopt, _ = G.autotune(troots[:16], mode="single", max_trials=24, stream=sp)
+    sopt, srep = G.autotune(troots[:16], mode="single", max_trials=24, stream=sp, table=table,
+                            write_table=write_table)
     skw = {kk: vv for kk, vv in sopt.items() if kk in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
                                                        "words_per_wave", "bu_serial_probes", "alpha_binned")}
     # single-root runs (warm-up pass adapts the launch depth), then timed
@@ -145,7 +151,7 @@ def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
             b.record(stream)
             stream.synchronize()
             t_single[rep, i] = a.elapsed_time(b)
-    bopt, brep = G.autotune(troots, mode="batch", max_trials=24, stream=sp)
+    bopt, brep = G.autotune(troots, mode="batch", max_trials=24, stream=sp, table=table, write_table=write_table)
     bkw = {kk: vv for kk, vv in bopt.items() if kk in ("alpha", "beta", "grid_blocks", "words_per_wave")}
     G.run_batch(roots, blv, bpa, stream=sp, **bkw)      # warm-up, adapts the batch depth
     # the timed group is one hipGraph launch (captured by the first replay)
@@ -169,7 +175,7 @@ def batched_leg(torch, hybfs, dev, workload="kron22", k=64, reps=3):
             "gteps_batch": round(sum(te) / (tb * 1e-3) / 1e9, 2),
             "gteps_single_aggregate": round(sum(te) / (ts * 1e-3) / 1e9, 2), "outputs_equal": equal,
             "batch_options": bkw, "batch_launch": "hipGraph replay", "single_options": skw,
-            "tune_trials": brep["trials"]}
+            "tune_trials": brep["trials"], "tune_source": {"single": srep["source"], "batch": brep["source"]}}
 
 
 SERVE_GRAPHS = ["kron14", "kron16", "kron18", "kron20", "kron22", "er20"]
@@ -657,11 +663,13 @@ def single_root_leg(torch, hybfs, dev, workload, args, nroots, cpu_budget_s, bal
         s_ = int(workload[4:]) if workload.startswith("kron") else 20
         troots = inputs.pick_roots(g, 16, inputs.ROOT_SEED.get(s_, 2020) + 500)
         t0 = time.time()
-        topt, trep = G.autotune(troots, mode="single", max_trials=args.tune_trials, stream=sp)
+        topt, trep = G.autotune(troots, mode="single", max_trials=args.tune_trials, stream=sp,
+                                table=None if args.retune else args.tune_table, write_table=args.write_tune_table)
         kw = {k: v for k, v in topt.items() if k in ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks",
                                                        "words_per_wave", "bu_serial_probes", "alpha_binned")}
-        tuning = {"options": kw, "trials": trep["trials"], "tune_roots": len(troots),
-                  "speedup_on_tune_roots": round(trep["start_us"] / trep["best_us"], 3)}
+        tuning = {"options": kw, "source": trep["source"], "trials": trep["trials"], "tune_roots": len(troots),
+                  "speedup_on_tune_roots": (round(trep["start_us"] / trep["best_us"], 3)
+                                            if trep["source"] == "tuned" else None)}
         log(f"autotune {time.time() - t0:.1f}s: {tuning}")
     lv = torch.empty(g.n, dtype=torch.int32, device=dev)
     pa = torch.empty(g.n, dtype=torch.int32, device=dev)
@@ -859,6 +867,10 @@ def main():
     ap.add_argument("--layer-table", type=int, default=0,
                     help="also print the per-layer breakdown of this many roots (stderr and JSON)")
     ap.add_argument("--tune-trials", type=int, default=48)
+    ap.add_argument("--tune-table", default=TUNE_TABLE,
+                    help="persisted autotune table: an entry for a graph, device and mode replaces tuning")
+    ap.add_argument("--retune", action="store_true", help="tune even where the table has an entry")
+    ap.add_argument("--write-tune-table", default=None, help="record what tuning finds in this table")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-host-out", action="store_true",
                     help="skip the host-output leg (runs that include the device-to-host copy)")
@@ -990,7 +1002,8 @@ def main():
         log("scale26:", {k: s26[k] for k in ("value", "median_root_us", "parity_all_roots", "roofline")})
     if not args.no_batch and args.workload == "kron20":
         log("batched leg (SCALE 22, 64 roots) ...")
-        out["batched"] = batched_leg(torch, hybfs, dev)
+        out["batched"] = batched_leg(torch, hybfs, dev, table=None if args.retune else args.tune_table,
+                                     write_table=args.write_tune_table)
         log("batched:", out["batched"])
     if not args.no_serve and args.workload == "kron20":
         log("serving leg (6 graphs) ...")

@@ -46,6 +46,7 @@ extern "C" {
 #define BFS_E_BUSY      (-4)  /* queue full (serving) */
 #define BFS_E_NOTFOUND  (-5)  /* unknown graph id or ticket */
 #define BFS_E_TIMEOUT   (-6)  /* a wait timed out */
+#define BFS_E_IO        (-7)  /* a file could not be read or written */
 
 typedef struct bfs_graph *bfs_graph_t;
 
@@ -352,6 +353,41 @@ typedef struct bfs_tune_report {
 
 int bfs_autotune(bfs_graph_t g, const int32_t *roots, int32_t k, int32_t mode, int32_t max_trials,
                  bfs_options *opt, bfs_tune_report *report);
+
+/* ---- persisted autotune table ----
+ * Tuned options outlive the process in a table file: JSON lines, one object
+ * per tuned graph, device and mode, with the key fields (and the graph's
+ * SCALE = ceil(log2 n) and edgefactor = round(nnz / 2n), for the reader),
+ * the tuned options and the tuned time.  MAX_POS (Section 5.2) and the
+ * switch parameters of Algorithm 3 are per-graph, per-machine constants,
+ * which is what the table keeps. */
+typedef struct bfs_tune_key {
+    int64_t n, nnz;          /* the graph's vertices and stored entries */
+    int64_t max_degree;      /* its largest row */
+    int64_t isolated;        /* its vertices without edges */
+    int32_t cus;             /* compute units of the device it was tuned on */
+    int32_t mode;            /* 0 single-root, 1 batched (as bfs_autotune) */
+} bfs_tune_key;
+
+/* The key of graph g on its device for a mode.  Errors: BFS_E_INVALID. */
+int bfs_tune_key_get(bfs_graph_t g, int32_t mode, bfs_tune_key *key);
+
+/* Look the key up in the table at `path` (a host file path).  On a hit the
+ * tuned fields of *opt (alpha, beta, probe_k, td_hub_degree, grid_blocks,
+ * words_per_wave, bu_serial_probes, alpha_binned) are overwritten and the
+ * rest kept, and *best_us (may be NULL) receives the stored time; of several
+ * entries with the key the last one counts, and lines that do not parse or
+ * hold invalid options are skipped.  Errors: BFS_E_NOTFOUND (no such entry,
+ * or no such file), BFS_E_INVALID (NULL argument), BFS_E_IO (unreadable). */
+int bfs_tune_table_get(const char *path, const bfs_tune_key *key, bfs_options *opt, double *best_us);
+
+/* Record *opt's tuned fields under the key in the table at `path`,
+ * replacing any entry with the same key and keeping the others; the file is
+ * rewritten through a temporary file in the same directory and renamed, so
+ * a reader never sees a partial table.  Calls in one process are
+ * serialised.  Errors: BFS_E_INVALID (NULL argument, invalid options),
+ * BFS_E_IO (the file or its temporary cannot be written). */
+int bfs_tune_table_put(const char *path, const bfs_tune_key *key, const bfs_options *opt, double best_us);
 
 /* ---- serving (continuous batching over resident graphs) ----
  *

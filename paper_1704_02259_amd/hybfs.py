@@ -19,6 +19,7 @@ BFS_E_DEVICE = -3
 BFS_E_BUSY = -4
 BFS_E_NOTFOUND = -5
 BFS_E_TIMEOUT = -6
+BFS_E_IO = -7
 
 BFS_GRAPH_DEVICE_INPUT = 1
 BFS_GRAPH_ASSUME_VALID = 2
@@ -86,6 +87,11 @@ class bfs_serve_report(ctypes.Structure):
                                                "gteps")] + [("evictions", ctypes.c_int64)]
 
 
+class bfs_tune_key(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
+                ("isolated", ctypes.c_int64), ("cus", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
 class bfs_tune_report(ctypes.Structure):
     _fields_ = [("trials", ctypes.c_int32), ("rounds", ctypes.c_int32), ("start_us", ctypes.c_double),
                 ("best_us", ctypes.c_double)]
@@ -140,6 +146,11 @@ def load():
         "bfs_graph_sync": (ctypes.c_int, [vp, vp]),
         "bfs_run_noalloc": (ctypes.c_int, [vp, i32, vp, vp, ctypes.POINTER(bfs_options),
                                            ctypes.POINTER(bfs_stats)]),
+        "bfs_tune_key_get": (ctypes.c_int, [vp, i32, ctypes.POINTER(bfs_tune_key)]),
+        "bfs_tune_table_get": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(bfs_tune_key),
+                                              ctypes.POINTER(bfs_options), ctypes.POINTER(ctypes.c_double)]),
+        "bfs_tune_table_put": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(bfs_tune_key),
+                                              ctypes.POINTER(bfs_options), ctypes.c_double]),
         "bfs_autotune": (ctypes.c_int, [vp, vp, i32, i32, i32, ctypes.POINTER(bfs_options),
                                         ctypes.POINTER(bfs_tune_report)]),
         "bfs_serve_config_init": (None, [ctypes.POINTER(bfs_serve_config)]),
@@ -332,16 +343,35 @@ class Graph:
                                    "layers": stats_layers(st, arr)}
         return level, parent
 
-    def autotune(self, roots, mode: str = "single", max_trials: int = 60, stream=None, **kw):
+    def autotune(self, roots, mode: str = "single", max_trials: int = 60, stream=None, table=None,
+                 write_table=None, **kw):
         """bfs_autotune: returns (options as a dict of keyword arguments for
-        run()/run_batch(), report dict)."""
-        r = np.ascontiguousarray(np.asarray(roots, dtype=np.int32).reshape(-1))
+        run()/run_batch(), report dict).  With `table` (a tune-table path) an
+        entry for this graph, device and mode is used instead of tuning
+        (report["source"] says which); `write_table` records what tuning
+        found."""
+        m = 0 if mode == "single" else 1
         opt = bfs_options_init(stream=stream, **kw)
+        key = bfs_tune_key()
+        _check(load().bfs_tune_key_get(self.handle, m, ctypes.byref(key)))
+        if table:
+            t = ctypes.c_double(0.0)
+            rc = load().bfs_tune_table_get(os.fsencode(table), ctypes.byref(key), ctypes.byref(opt), ctypes.byref(t))
+            if rc == BFS_OK:
+                return ({k: getattr(opt, k) for k in OPTION_KNOBS},
+                        {"trials": 0, "rounds": 0, "start_us": 0.0, "best_us": t.value, "source": "table"})
+            if rc != BFS_E_NOTFOUND:
+                _check(rc)
+        r = np.ascontiguousarray(np.asarray(roots, dtype=np.int32).reshape(-1))
         rep = bfs_tune_report()
-        _check(load().bfs_autotune(self.handle, r.ctypes.data, len(r), 0 if mode == "single" else 1, max_trials,
-                                   ctypes.byref(opt), ctypes.byref(rep)))
+        _check(load().bfs_autotune(self.handle, r.ctypes.data, len(r), m, max_trials, ctypes.byref(opt),
+                                   ctypes.byref(rep)))
+        if write_table:
+            _check(load().bfs_tune_table_put(os.fsencode(write_table), ctypes.byref(key), ctypes.byref(opt),
+                                             rep.best_us))
         return ({k: getattr(opt, k) for k in OPTION_KNOBS},
-                {"trials": rep.trials, "rounds": rep.rounds, "start_us": rep.start_us, "best_us": rep.best_us})
+                {"trials": rep.trials, "rounds": rep.rounds, "start_us": rep.start_us, "best_us": rep.best_us,
+                 "source": "tuned"})
 
     def run_batch(self, roots, level=None, parent=None, stream=None, stats: bool = False, **kw):
         """Batched BFS from every root in `roots` (bfs_run_batch).  Outputs are

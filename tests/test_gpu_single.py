@@ -509,3 +509,25 @@ def test_library_first_then_torch():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
     assert out.returncode == 0 and out.stdout.strip().endswith("ok"), out.stdout[-2000:] + out.stderr[-2000:]
+
+
+def test_autotune_table_round_trip(torch, hyb, tmp_path):
+    """Tuning records its options in a table; a later call with the table
+    returns them without tuning, and they leave the results unchanged."""
+    g = inputs.kronecker(14)
+    G = hyb.Graph.from_csr(g)
+    roots = [int(r) for r in inputs.pick_roots(g, 8, 1414)]
+    table = str(tmp_path / "tune.jsonl")
+    o1, r1 = G.autotune(roots, max_trials=8, table=table, write_table=table)
+    assert r1["source"] == "tuned" and r1["trials"] >= 1
+    o2, r2 = G.autotune(roots, max_trials=8, table=table)
+    assert r2["source"] == "table" and r2["trials"] == 0 and o2 == o1
+    assert abs(r2["best_us"] - r1["best_us"]) < 1e-2
+    ob, rb = G.autotune(roots, mode="batch", max_trials=4, table=table, write_table=table)
+    assert rb["source"] == "tuned"                      # the batched mode has its own entry
+    assert G.autotune(roots, mode="batch", table=table)[1]["source"] == "table"
+    kw = {k: v for k, v in o2.items() if k not in ("rule",)}
+    for r in roots[:3]:
+        lv, pa, st = _gpu_bfs(torch, G, r, **kw)
+        _check_against_oracle(g, r, lv, pa)
+    G.close()
