@@ -235,6 +235,36 @@ def test_cached_workspaces_stay_within_budget(torch, hyb, graphs):
         G.close()
 
 
+def test_host_output_batches_share_a_small_budget(torch, hyb, graphs):
+    """Host outputs: a batch of k roots stages its outputs in an 8·k·n-byte
+    device buffer that its slot keeps.  Two slots taking batches of up to 8
+    under a budget of 1.5 batch footprints must release each other's idle
+    staging and workspaces or wait; every answer still equals the oracle's."""
+    gs, Gs = graphs
+    g16, G16 = gs[3], Gs[3]
+    info = G16.info()
+    batch = info.batch_workspace_bytes + 8 * 8 * g16.n
+    single = info.workspace_bytes + (g16.n + 64) * 8
+    budget = int(1.5 * max(batch, single))
+    S = hyb.hybfs.Server(streams=2, max_batch=8, batch_threshold=2, out_on_device=0, memory_budget=budget)
+    gid = S.add_graph(G16)
+    live = np.nonzero(np.diff(g16.off) > 0)[0]
+    roots = [int(x) for x in np.random.default_rng(16).choice(live, 64)]
+    bufs = [(np.full(g16.n, 7, np.int32), np.full(g16.n, 7, np.int32)) for _ in roots]
+    tickets = [S.submit(gid, r, lv.ctypes.data, pa.ctypes.data) for r, (lv, pa) in zip(roots, bufs)]
+    for t in tickets:
+        S.wait(t)
+    st = S.stats()
+    _say("host-output batch stats", st)
+    assert st["completed"] == len(roots) and st["failed"] == 0
+    assert st["batched_requests"] > 0
+    assert st["peak_bytes"] <= budget
+    for r, (lv, pa) in zip(roots, bufs):
+        olv, opa = oracle.bfs(g16, r)
+        assert np.array_equal(lv, olv) and np.array_equal(pa, opa), r
+    S.close()
+
+
 def test_paced_stream_and_poll(torch, hyb, graphs):
     gs, Gs = graphs
     S = hyb.hybfs.Server(streams=3)
