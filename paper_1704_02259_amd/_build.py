@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhybfs.so")
 SOURCES = ["hybfs_api.cpp", "hybfs_batch.cpp", "hybfs_serve.cpp", "hybfs_tune.cpp", "hybfs_noalloc.cpp",
            "hybfs_table.cpp",
-           "bfs_kernels.hip",
+           "bfs_kernels.hip", "bfs_util.hip",
            "bfs_batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

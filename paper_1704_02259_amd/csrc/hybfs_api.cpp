@@ -170,8 +170,10 @@ int get_workspace(Graph *g, void *stream, Workspace **out)
     w->ctrl = (Ctrl *)(b + o);               o += align256(sizeof(Ctrl));
     w->trace = (LayerRec *)(b + o);          o += align256((size_t)kTraceCap * sizeof(LayerRec));
     w->filt = (unsigned *)(b + o);
-    if ((e = hipMemset(w->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return hip_fail(e, "workspace init");
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "workspace init");
+    // the workspace is used on `stream` only: a clear ordered on it suffices
+    // (no device-wide wait, which would stall the other streams' work)
+    if ((e = launch_zero(w->ctrl, align256(sizeof(Ctrl)), (hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "workspace init");
     *out = w.get();
     g->ws[stream] = std::move(w);
     return BFS_OK;
@@ -269,7 +271,7 @@ static size_t bin_bytes(const Graph *g)
     return 3 * align256((size_t)(g->nbins + 1) * 4) + (size_t)cap * 8;
 }
 
-static int ensure_bins(Graph *g, Workspace *w)
+static int ensure_bins(Graph *g, Workspace *w, hipStream_t s)
 {
     if (w->bin_buf) return BFS_OK;
     const long long cap = std::max<long long>(1, std::min<long long>(g->nnz, 1LL << 28));
@@ -284,8 +286,7 @@ static int ensure_bins(Graph *g, Workspace *w)
     w->bin_cur = (int *)(b + 2 * a);
     w->bin_pairs = (unsigned long long *)(b + 3 * a);
     w->bin_cap = cap;
-    if ((e = hipMemset(w->bin_cnt, 0, a)) != hipSuccess) return hip_fail(e, "bucket init");
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "bucket init");
+    if ((e = launch_zero(w->bin_cnt, a, s)) != hipSuccess) return hip_fail(e, "bucket init");
     return BFS_OK;
 }
 
@@ -432,7 +433,7 @@ int enqueue_traversal(Graph *g, Workspace *w, const bfs_options &opt, int root, 
     // binned top-down: allowed on the layers after which its kernels are enqueued
     const bool bins = g->nbins <= kMaxBins && (opt.td_binned > 0 || (opt.td_binned == 0 && g->bin_auto));
     if (bins) {
-        const int rc = ensure_bins(g, w);
+        const int rc = ensure_bins(g, w, s);
         if (rc) return rc;
     }
     if (!w->no_alloc) {
@@ -504,7 +505,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
 {
     const bool bins = g->nbins <= kMaxBins && (opt.td_binned > 0 || (opt.td_binned == 0 && g->bin_auto));
     if (bins) {
-        const int rc = ensure_bins(g, w);
+        const int rc = ensure_bins(g, w, s);
         if (rc) return rc;
     }
     {

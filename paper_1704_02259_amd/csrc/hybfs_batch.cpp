@@ -63,8 +63,9 @@ int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
     w->ctrl = (BCtrl *)(b + o);              o += align256(sizeof(BCtrl));
     w->trace = (LayerRec *)(b + o);          o += align256((size_t)kTraceCap * sizeof(LayerRec));
     w->tab = (int **)(b + o);
-    if ((e = hipMemset(w->ctrl, 0, sizeof(BCtrl))) != hipSuccess) return hip_fail(e, "workspace init");
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "workspace init");
+    // used on `stream` only: a clear ordered on it suffices
+    if ((e = launch_zero(w->ctrl, align256(sizeof(BCtrl)), (hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "workspace init");
     *out = w.get();
     g->bws[stream] = std::move(w);
     return BFS_OK;

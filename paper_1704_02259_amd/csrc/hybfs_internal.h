@@ -176,6 +176,10 @@ size_t queue_bytes(const Graph *g, bool queues, bool hub_lists);
 // record cleared; BFS_OK when there were none.
 int check_async_errors(Graph *g, void *stream);
 size_t batch_workspace_bytes(const Graph *g);
+// Zeroes `bytes` (a multiple of 8) at p on stream s (bfs_util.hip): a kernel
+// rather than a memset, so that a caller capturing the stream records no
+// memset node.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 // Device bytes the workspaces of g for `stream` hold (single-root and
 // batched, each optionally returned), and their release (the stream must be
 // idle, the workspaces unused); the device bytes the single-root workspace of
