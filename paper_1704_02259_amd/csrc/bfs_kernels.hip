@@ -603,10 +603,55 @@ __device__ __forceinline__ void bu_finish_vertex(const Params &P, const unsigned
             if (found || s + p0 + 4 >= e) live = false;
         }
     }
-    // phase 2: the rest of each unresolved row, one row at a time
+    // phase 2: the rest of each unresolved row.  Rows with at most 32 entries
+    // left go two to a step, one per half-wavefront; the others one at a time
+    // over the whole wavefront.
     const int KP = max(K, KS);
-    unsigned long long rem = __ballot(need_s && !found && dg > KP);
+    const bool cont = need_s && !found && dg > KP;
+    unsigned long long rem = __ballot(cont);
     if (P.count && lane == 0) wc.c[2] += __popcll(rem);
+    unsigned long long shrt = __ballot(cont && dg - KP <= 32);
+    rem &= ~shrt;
+    while (shrt) {
+        const int ka = __ffsll((long long)shrt) - 1;
+        shrt &= shrt - 1;
+        int kb = -1;
+        if (shrt) {
+            kb = __ffsll((long long)shrt) - 1;
+            shrt &= shrt - 1;
+        }
+        const long long sa = bcast64(s, ka) + KP, ea = bcast64(e, ka);
+        long long sb = 0, eb = 0;
+        if (kb >= 0) {
+            sb = bcast64(s, kb) + KP;
+            eb = bcast64(e, kb);
+        }
+        const bool hi = lane >= 32;
+        const long long j = (hi ? sb : sa) + (lane & 31);
+        const long long ej = hi ? eb : ea;
+        int u = 0;
+        bool hit = false;
+        if (j < ej) {
+            u = P.col[j];
+            hit = probe_front(front, lf, u);
+        }
+        if (P.count) {
+            wc.c[3] += lane == 0;
+            wc.c[4] += j < ej;
+        }
+        const unsigned long long hb = __ballot(hit);
+        const unsigned long long hlo = hb & 0xFFFFFFFFull, hhi = hb >> 32;
+        const int hva = hlo ? __builtin_amdgcn_readlane(u, __ffsll((long long)hlo) - 1) : -1;
+        const int hvb = hhi ? __builtin_amdgcn_readlane(u, 32 + __ffsll((long long)hhi) - 1) : -1;
+        if (lane == ka && hva >= 0) {
+            found = true;
+            par = hva;
+        }
+        if (lane == kb && hvb >= 0) {
+            found = true;
+            par = hvb;
+        }
+    }
     while (rem) {
         const int k = __ffsll((long long)rem) - 1;
         rem &= rem - 1;
