@@ -153,9 +153,11 @@ typedef struct bfs_options {
                                   (synchronous runs with stats only) */
     int32_t graph_launch;      /* 1: replay a hipGraph of the launch sequence,
                                   captured once per workspace and option set, with
-                                  only the root and the output pointers updated per
-                                  run; 0 (default): enqueue the kernels one by one
-                                  (measured faster on MI355X for this sequence) */
+                                  only the root(s) and the output pointers updated
+                                  per run (bfs_run: one traversal; bfs_run_batch:
+                                  each group of up to 64 roots); 0 (default):
+                                  enqueue the kernels one by one (measured as fast
+                                  on MI355X for these sequences) */
     int32_t td_binned;         /* large top-down layers bucketed by destination tile
                                   (parents by LDS minimum, outputs written tile by
                                   tile): 0 (default) = for graphs of at least 2^23
