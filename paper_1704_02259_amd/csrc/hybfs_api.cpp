@@ -537,6 +537,11 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         R.params.parent = par;
         R.fused = fused;
         if ((e = hipGraphCreate(&R.graph, 0)) != hipSuccess) return hip_fail(e, "graph create");
+        // a graph that could not be built completely is destroyed
+        auto fail = [&](hipError_t err, const char *what) {
+            hipGraphDestroy(R.graph);
+            return hip_fail(err, what);
+        };
         std::vector<int> layer_idx(L);
         for (int i = 0; i < L; ++i) layer_idx[i] = i;
         hipGraphNode_t prev = nullptr;
@@ -549,7 +554,7 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
         kp.blockDim = dim3(kBlock);
         kp.kernelParams = fused ? init_fused_args : init_args;
         if ((e = hipGraphAddKernelNode(&R.init, R.graph, nullptr, 0, &kp)) != hipSuccess)
-            return hip_fail(e, "graph init node");
+            return fail(e, "graph init node");
         prev = R.init;
         auto add = [&](void *fn, dim3 gd, dim3 bd, void **args) -> hipError_t {
             hipKernelNodeParams np;
@@ -569,22 +574,22 @@ int enqueue_traversal_graph(Graph *g, Workspace *w, const bfs_options &opt, int 
             void *args[] = {&R.params, &layer_idx[i], &allow[i]};
             if ((e = add(kernel_ptr_layer(R.params.wide != 0, layer_build(R.params, i), layer_filter(R.params, i)),
                          dim3(grid), dim3(kBlock), args)) != hipSuccess)
-                return hip_fail(e, "graph layer node");
+                return fail(e, "graph layer node");
             if (allow[i]) {
                 void *bargs[] = {&R.params, &layer_idx[i]};
                 if ((e = add(kernel_ptr_bin_scan(), dim3(1), dim3(kFinishBlock), bargs)) != hipSuccess ||
                     (e = add(kernel_ptr_bin_scatter(), dim3(grid), dim3(kBlock), bargs)) != hipSuccess ||
                     (e = add(kernel_ptr_bin_reduce(), dim3(2 * g->cus), dim3(kReduceBlockThreads), bargs)) !=
                         hipSuccess)
-                    return hip_fail(e, "graph binned nodes");
+                    return fail(e, "graph binned nodes");
             }
         }
         void *fin_args[] = {&R.params};
         if ((e = add(kernel_ptr_finish(finish_build(R.params)), dim3(1), dim3(kFinisherBlock), fin_args)) !=
             hipSuccess)
-            return hip_fail(e, "graph finisher node");
+            return fail(e, "graph finisher node");
         if ((e = hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0)) != hipSuccess)
-            return hip_fail(e, "graph instantiate");
+            return fail(e, "graph instantiate");
         it = w->replays.emplace(key, R).first;
     }
     Workspace::Replay &R = it->second;

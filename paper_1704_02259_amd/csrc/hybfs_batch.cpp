@@ -191,19 +191,24 @@ int enqueue_batch_graph(Graph *g, BatchWorkspace *w, const bfs_options &opt, con
         void *init_args[] = {&P, &o};
         void *seed_args[] = {&P, &R};
         void *fin_args[] = {&P};
+        // a graph that could not be built completely is destroyed
+        auto fail = [&](hipError_t err, const char *what) {
+            hipGraphDestroy(Q.graph);
+            return hip_fail(err, what);
+        };
         if ((e = add(BK_INIT, dim3(grid, k + 1), dim3(kBlock), init_args, &Q.init)) != hipSuccess ||
             (e = add(BK_SEED, dim3(1), dim3(64), seed_args, &Q.seed)) != hipSuccess)
-            return hip_fail(e, "graph batch nodes");
+            return fail(e, "graph batch nodes");
         for (int i = 0; i < L; ++i) {
             void *args[] = {&P, &layer_idx[i]};
             if ((e = add(BK_PUSH, dim3(grid), dim3(kBlock), args, nullptr)) != hipSuccess ||
                 (e = add(BK_PULL, dim3(pgrid), dim3(kPullWaves * 64), args, nullptr)) != hipSuccess)
-                return hip_fail(e, "graph batch layer nodes");
+                return fail(e, "graph batch layer nodes");
         }
         if ((e = add(BK_FINISH, dim3(1), dim3(kFinishBlock), fin_args, nullptr)) != hipSuccess)
-            return hip_fail(e, "graph batch finisher node");
+            return fail(e, "graph batch finisher node");
         if ((e = hipGraphInstantiate(&Q.exec, Q.graph, nullptr, nullptr, 0)) != hipSuccess)
-            return hip_fail(e, "graph instantiate");
+            return fail(e, "graph instantiate");
         it = w->replays.emplace(key, Q).first;
     }
     BatchWorkspace::Replay &Q = it->second;
