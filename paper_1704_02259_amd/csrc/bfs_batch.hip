@@ -87,14 +87,24 @@ static __device__ __forceinline__ void td_discover(const BParams &P, unsigned lo
                                                    unsigned long long *unext, int v, int u, int d,
                                                    unsigned long long m)
 {
-    const unsigned long long old = atomicOr(&next[v], m);
-    if (old == 0) atomicOr(&unext[v >> 6], 1ull << (v & 63));
+    // plain reads first: next[v] only gains bits and parents only decrease,
+    // so a stale read can only cost an unneeded atomic, never skip a needed one
+    unsigned long long old = next[v];
+    if ((old & m) != m) {
+        old = atomicOr(&next[v], m);
+        if (old == 0) atomicOr(&unext[v >> 6], 1ull << (v & 63));
+    }
     const unsigned long long fresh = m & ~old;
     while (m) {
         const int b = __ffsll((long long)m) - 1;
         m &= m - 1;
-        atomicMin((unsigned *)&P.par[b][v], (unsigned)u);
-        if ((fresh >> b) & 1ull) P.lvl[b][v] = d + 1;
+        unsigned *pp = (unsigned *)&P.par[b][v];
+        if ((fresh >> b) & 1ull) {
+            atomicMin(pp, (unsigned)u);
+            P.lvl[b][v] = d + 1;
+        } else if (*pp > (unsigned)u) {
+            atomicMin(pp, (unsigned)u);
+        }
     }
 }
 
