@@ -884,11 +884,11 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--layer-profile", type=int, default=0,
                     help="only the per-layer profile of this many roots of --workload (writes --layer-map)")
-    ap.add_argument("--layer-map", default="gpurun_out/layer_map.json")
+    ap.add_argument("--layer-map", default="layer_map.json")
     ap.add_argument("--batch-profile", type=int, default=0,
                     help="N plain batches of the 64 workload roots, then one with per-layer events")
     ap.add_argument("--batch-workload", default="kron22")
-    ap.add_argument("--batch-map", default="gpurun_out/batch_map.json")
+    ap.add_argument("--batch-map", default="batch_map.json")
     ap.add_argument("--join-batch-counters", nargs="*", default=None,
                     help="kernel-trace / counter CSVs of a --batch-profile run: per-dispatch table")
     ap.add_argument("--join-counters", nargs="*", default=None,
