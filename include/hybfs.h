@@ -155,7 +155,9 @@ typedef struct bfs_options {
                                   captured once per workspace and option set, with
                                   only the root(s) and the output pointers updated
                                   per run (bfs_run: one traversal; bfs_run_batch:
-                                  each group of up to 64 roots); 0 (default):
+                                  each group of up to 64 roots); runs with
+                                  profile_layers launch directly (the per-layer
+                                  events sit between the launches); 0 (default):
                                   enqueue the kernels one by one (measured as fast
                                   on MI355X for these sequences) */
     int32_t td_binned;         /* large top-down layers bucketed by destination tile
