@@ -607,10 +607,15 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P, LaneP
         int *pa = out.parent[y];
         const bool vec = ((((unsigned long long)lv) | ((unsigned long long)pa)) & 15ull) == 0;
         const long long n4 = vec ? (P.n >> 2) : 0;
-        const int4 m1 = make_int4(-1, -1, -1, -1);
+        // non-temporal 16-byte stores: the 8·k·n bytes of -1 are not read
+        // again by this kernel, and keeping them out of L2 left more of it to
+        // the layers (whole batch 0.6% faster at SCALE 22, though this kernel
+        // itself runs a little longer)
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        const v4i m1 = {-1, -1, -1, -1};
         for (long long i = gt; i < n4; i += nt) {
-            ((int4 *)lv)[i] = m1;
-            ((int4 *)pa)[i] = m1;
+            __builtin_nontemporal_store(m1, (v4i *)lv + i);
+            __builtin_nontemporal_store(m1, (v4i *)pa + i);
         }
         for (long long i = (n4 << 2) + gt; i < P.n; i += nt) {
             lv[i] = -1;
