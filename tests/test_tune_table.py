@@ -7,6 +7,8 @@ from __future__ import annotations
 
 import ctypes
 import json
+import math
+import sys
 
 import pytest
 
@@ -101,3 +103,106 @@ def test_invalid_arguments(lib, tmp_path):
     assert not p.exists()
     assert _put(lib, tmp_path / "no_such_dir" / "t.jsonl", k, 1.0) == hybfs.BFS_E_IO
     assert lib.bfs_tune_key_get(None, 0, ctypes.byref(k)) == hybfs.BFS_E_INVALID
+
+
+
+_KEY_FIELDS = {"n": 1 << 20, "nnz": 31399680, "max_degree": 70000, "isolated": 300000, "cus": 256, "mode": 0}
+_TUNED = ("alpha", "beta", "probe_k", "td_hub_degree", "grid_blocks", "words_per_wave", "bu_serial_probes",
+          "alpha_binned")
+
+
+def _whole(v):
+    """The integer a JSON value stands for, else None (integral floats count)."""
+    if isinstance(v, bool) or not isinstance(v, (int, float)):
+        return None
+    if isinstance(v, float) and (not math.isfinite(v) or v != math.floor(v)):
+        return None
+    return int(v) if abs(v) <= 9e15 else None
+
+
+def _valid(o):
+    """The ranges the library accepts for the tuned fields."""
+    w = o["words_per_wave"]
+    return (o["alpha"] > 0 and o["beta"] > 0 and 0 <= o["probe_k"] <= 64 and 256 <= o["td_hub_degree"] <= 1 << 24
+            and o["grid_blocks"] >= 0 and 0 <= w <= 64 and w & (w - 1) == 0 and -1 <= o["bu_serial_probes"] <= 1
+            and o["alpha_binned"] >= 0)
+
+
+def _expected(lines):
+    """The entry a lookup of the test key returns: the last line that is a JSON
+    object with the key, every tuned field a 32-bit integer, a finite best_us
+    that does not underflow, and valid options."""
+    found = None
+    for line in lines:
+        try:
+            d = json.loads(line)
+        except ValueError:
+            continue
+        if not isinstance(d, dict) or any(_whole(d.get(k)) != v for k, v in _KEY_FIELDS.items()):
+            continue
+        o = {f: _whole(d.get(f)) for f in _TUNED}
+        t = d.get("best_us")
+        if any(v is None or not -2**31 <= v < 2**31 for v in o.values()) or not _valid(o):
+            continue
+        if isinstance(t, bool) or not isinstance(t, (int, float)) or not math.isfinite(t):
+            continue
+        if t != 0 and abs(t) < sys.float_info.min:
+            continue
+        found = (o, float(t))
+    return found
+
+
+def test_reader_matches_a_model_of_the_format(lib, tmp_path):
+    """Lookups over generated files agree with a Python model of the format
+    (any text, JSON objects with arbitrary fields, entries of the key with
+    valid and invalid options); a put then replaces every entry of the key."""
+    from hypothesis import given, settings, strategies as st
+
+    key = _key()
+    p = tmp_path / "t.jsonl"
+    anyval = st.one_of(st.integers(-2**40, 2**40), st.floats(allow_nan=True, allow_infinity=True),
+                       st.text(max_size=6), st.booleans())
+    names = list(_KEY_FIELDS) + list(_TUNED) + ["best_us"]
+    noise = st.dictionaries(st.sampled_from(names), anyval, max_size=len(names)).map(json.dumps)
+    good = {"alpha": st.integers(1, 80), "beta": st.integers(1, 40), "probe_k": st.integers(0, 64),
+            "td_hub_degree": st.sampled_from([256, 1024, 1 << 24]), "grid_blocks": st.integers(0, 2048),
+            "words_per_wave": st.sampled_from([0, 1, 2, 4, 8, 16, 32, 64]), "bu_serial_probes": st.integers(-1, 1),
+            "alpha_binned": st.integers(0, 12)}
+    bad = {"alpha": st.integers(-2, 0), "beta": st.integers(-2, 0), "probe_k": st.sampled_from([-1, 65]),
+           "td_hub_degree": st.sampled_from([255, (1 << 24) + 1]), "grid_blocks": st.just(-1),
+           "words_per_wave": st.sampled_from([-1, 3, 12, 65, 128]), "bu_serial_probes": st.sampled_from([-2, 2]),
+           "alpha_binned": st.just(-1)}
+
+    @st.composite
+    def entry(draw):
+        d = dict(_KEY_FIELDS)
+        if draw(st.integers(0, 5)) == 0:                 # another key, or a key field that is not a whole number
+            d[draw(st.sampled_from(list(_KEY_FIELDS)))] = draw(st.one_of(st.integers(0, 3), st.floats()))
+        broken = draw(st.sampled_from(_TUNED)) if draw(st.booleans()) else None
+        for f in _TUNED:
+            v = draw((bad if f == broken else good)[f])
+            d[f] = float(v) if draw(st.integers(0, 9)) == 0 else v
+        d["best_us"] = draw(st.one_of(st.floats(0, 1e4), st.floats(allow_nan=True, allow_infinity=True)))
+        if draw(st.integers(0, 9)) == 0:
+            del d[draw(st.sampled_from(sorted(d)))]
+        return json.dumps(d)
+
+    line = st.one_of(st.text(max_size=80), noise, entry())
+
+    @settings(max_examples=400, deadline=None)
+    @given(st.lists(line, max_size=6), st.integers(1, 64), st.sampled_from([0, 1, 2, 4, 8, 16, 32, 64]))
+    def run(lines, alpha, wpw):
+        p.write_text("\n".join(lines) + "\n")
+        rc, o, t = _get(lib, p, key)
+        want = _expected(lines)
+        if want is None:
+            assert rc == hybfs.BFS_E_NOTFOUND
+        else:
+            assert rc == hybfs.BFS_OK
+            assert {f: getattr(o, f) for f in _TUNED} == want[0] and t == want[1]
+        assert _put(lib, p, key, 3.0, alpha=alpha, words_per_wave=wpw) == hybfs.BFS_OK
+        rc, o, t = _get(lib, p, key)
+        assert rc == hybfs.BFS_OK and (o.alpha, o.words_per_wave, t) == (alpha, wpw, 3.0)
+        assert _expected(p.read_text().splitlines())[0]["alpha"] == alpha
+
+    run()
