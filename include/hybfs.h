@@ -388,9 +388,12 @@ int bfs_tune_table_get(const char *path, const bfs_tune_key *key, bfs_options *o
 /* Record *opt's tuned fields under the key in the table at `path`,
  * replacing any entry with the same key and keeping the others; the file is
  * rewritten through a temporary file in the same directory and renamed, so
- * a reader never sees a partial table.  Calls in one process are
- * serialised.  Errors: BFS_E_INVALID (NULL argument, invalid options),
- * BFS_E_IO (the file or its temporary cannot be written). */
+ * a reader never sees a partial table.  Calls are serialised, in one
+ * process by a mutex and across processes by an exclusive flock() on
+ * "<path>.lock" (created beside the table and left there), so concurrent
+ * puts of different keys all survive.  Errors: BFS_E_INVALID (NULL argument,
+ * invalid options), BFS_E_IO (the file, its temporary or the lock file
+ * cannot be written). */
 int bfs_tune_table_put(const char *path, const bfs_tune_key *key, const bfs_options *opt, double best_us);
 
 /* ---- serving (continuous batching over resident graphs) ----

@@ -1,6 +1,8 @@
 // Persisted autotune table (bfs_tune_table_*): JSON lines, one flat object
 // per (graph, device, mode) with integer fields and the tuned time.  Only
 // files of this form are read; any line that does not parse is skipped.
+#include <fcntl.h>
+#include <sys/file.h>
 #include <unistd.h>
 
 #include <cerrno>
@@ -19,6 +21,37 @@ namespace hybfs {
 namespace {
 
 std::mutex g_table_mu;   // puts in one process, one at a time
+
+// Exclusive advisory lock on "<path>.lock" for the lifetime of the object, so
+// that puts from different processes do not overwrite each other's entries
+// (each reads the table, then renames its rewritten copy over it).
+struct FileLock {
+    int fd = -1;
+    int err = 0;   // errno of a failed open or lock
+    explicit FileLock(const std::string &path)
+    {
+        fd = open((path + ".lock").c_str(), O_RDWR | O_CREAT | O_CLOEXEC, 0644);
+        if (fd < 0) {
+            err = errno;
+            return;
+        }
+        int rc;
+        do rc = flock(fd, LOCK_EX);
+        while (rc != 0 && errno == EINTR);
+        if (rc != 0) {
+            err = errno;
+            close(fd);
+            fd = -1;
+        }
+    }
+    ~FileLock()
+    {
+        if (fd >= 0) {
+            flock(fd, LOCK_UN);
+            close(fd);
+        }
+    }
+};
 
 // The tuned fields, in file order.
 struct Field {
@@ -172,6 +205,9 @@ int bfs_tune_table_put(const char *path, const bfs_tune_key *key, const bfs_opti
     if (rc) return rc;
     if (!std::isfinite(best_us) || best_us < 0) return set_error(BFS_E_INVALID, "best_us must be finite and >= 0");
     std::lock_guard<std::mutex> lk(g_table_mu);
+    const FileLock flk(path);
+    if (flk.fd < 0)
+        return set_error(BFS_E_IO, "cannot lock the tune table %s.lock: %s", path, std::strerror(flk.err));
     std::vector<std::string> keep;
     if (access(path, F_OK) == 0) {
         std::ifstream in(path);

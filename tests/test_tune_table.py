@@ -206,3 +206,45 @@ def test_reader_matches_a_model_of_the_format(lib, tmp_path):
         assert _expected(p.read_text().splitlines())[0]["alpha"] == alpha
 
     run()
+
+
+_WRITER = r"""
+import sys
+from paper_1704_02259_amd import hybfs
+import ctypes
+lib = hybfs.load()
+path, first, count = sys.argv[1], int(sys.argv[2]), int(sys.argv[3])
+for i in range(first, first + count):
+    k = hybfs.bfs_tune_key()
+    k.n, k.nnz, k.max_degree, k.isolated, k.cus, k.mode = 1000 + i, 16000, 90, 7, 256, 0
+    o = hybfs.bfs_options_init(alpha=1 + i % 60)
+    rc = lib.bfs_tune_table_put(path.encode(), ctypes.byref(k), ctypes.byref(o), float(i))
+    if rc != hybfs.BFS_OK:
+        sys.exit(f"put {i}: {rc} {lib.bfs_last_error().decode()}")
+"""
+
+
+def test_puts_from_several_processes_all_survive(lib, tmp_path):
+    """Processes that put different keys into one table at the same time
+    lose none of them: each put reads the table and renames a rewritten copy
+    over it under an exclusive lock on a file beside it."""
+    import os
+    import subprocess
+    import sys
+
+    p = tmp_path / "t.jsonl"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, PYTHONPATH=root + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    nproc, per = 4, 40
+    procs = [subprocess.Popen([sys.executable, "-c", _WRITER, str(p), str(i * per), str(per)], env=env,
+                              stdout=subprocess.PIPE, stderr=subprocess.STDOUT) for i in range(nproc)]
+    for pr in procs:
+        out, _ = pr.communicate(timeout=240)
+        assert pr.returncode == 0, out.decode()[-2000:]
+    rows = [json.loads(line) for line in p.read_text().splitlines()]
+    assert sorted(r["n"] for r in rows) == [1000 + i for i in range(nproc * per)]
+    for i in range(nproc * per):
+        k = _key(n=1000 + i, nnz=16000, md=90, iso=7)
+        rc, o, t = _get(lib, p, k)
+        assert rc == hybfs.BFS_OK and o.alpha == 1 + i % 60 and t == float(i)
+    assert not list(tmp_path.glob("*.tmp*"))
