@@ -956,7 +956,8 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     hybfs.load()
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.sweep:

@@ -112,7 +112,8 @@ def layer_replay(g, level: np.ndarray) -> dict:
                                       level.ctypes.data, cap,
                                       arrs["n_f"].ctypes.data, arrs["m_f"].ctypes.data,
                                       arrs["m_u"].ctypes.data, arrs["v_u"].ctypes.data)
-    assert got == L
+    if got != L:
+        raise RuntimeError(f"oracle_layer_replay returned {got} layers, expected {L}")
     return {k: v[:L] for k, v in arrs.items()}
 
 
