@@ -15,7 +15,10 @@
 //        the first u whose frontier mask holds lane b is lane b's parent.
 // Every block of both kernels reads the layer's counters and takes the same
 // direction decision (Algorithm 3 on counts over the union of the lanes'
-// frontiers), as in the single-root path.
+// frontiers), as in the single-root path.  The frontier masks of the first
+// kBatchHist layers are kept, and after the finisher a level pass stores
+// those layers' levels (and -1 where a root never arrived) in one coalesced
+// sweep; deeper levels are stored by the layers that reach them.
 #include "bfs_device.h"
 #include "bfs_wave.h"
 
@@ -54,6 +57,19 @@ static __device__ __forceinline__ int bdecide(const BParams &P, int cur, long lo
     return cur;
 }
 
+// Where F_d's lane masks live: the first P.hist layers keep their own slots
+// until the level pass has read them; later layers rotate through the three
+// slots after those.
+static __device__ __forceinline__ unsigned long long *fmask(const BParams &P, int d)
+{
+    const long long slot = d < P.hist ? d : P.hist + (d - P.hist) % 3;
+    return P.fm + slot * P.n;
+}
+
+// Whether level d is stored by the layer that reaches it (d >= P.hist); the
+// levels below P.hist are stored by the level pass from the kept masks.
+static __device__ __forceinline__ bool layer_stores_level(const BParams &P, int d) { return d >= P.hist; }
+
 // Lane b of `bits`: v's parent in root b's tree is u.  (The levels of a
 // bottom-up layer are stored afterwards, per lane across a word of vertices.)
 static __device__ __forceinline__ void emit_parent(const BParams &P, long long v, int u, unsigned long long bits)
@@ -70,6 +86,7 @@ static __device__ __forceinline__ void emit_parent(const BParams &P, long long v
 // bytes of root b's level array.  All lanes of the wavefront must be active.
 static __device__ __forceinline__ void store_levels(const BParams &P, long long v, int d, unsigned long long found)
 {
+    if (!layer_stores_level(P, d + 1)) return;   // wave-uniform
     unsigned long long all = wave_or_u64(found);
     while (all) {
         const int b = __ffsll((long long)all) - 1;
@@ -80,9 +97,9 @@ static __device__ __forceinline__ void store_levels(const BParams &P, long long 
 
 // Top-down edge u -> v for the lanes in m (u in their frontier, v not yet
 // visited by them): the lanes' parent of v is the smallest such u, taken by
-// an unsigned atomic minimum over the -1 the outputs start from; the first
-// edge to bring a lane stores its level, the first to reach v at all marks v
-// in the next frontier's bitmap.
+// an unsigned atomic minimum over the -1 the parents start from; the first
+// edge to bring a lane stores its level (when the layer stores levels), the
+// first to reach v at all marks v in the next frontier's bitmap.
 static __device__ __forceinline__ void td_discover(const BParams &P, unsigned long long *next,
                                                    unsigned long long *unext, int v, int u, int d,
                                                    unsigned long long m)
@@ -101,7 +118,7 @@ static __device__ __forceinline__ void td_discover(const BParams &P, unsigned lo
         unsigned *pp = (unsigned *)&P.par[b][v];
         if ((fresh >> b) & 1ull) {
             atomicMin(pp, (unsigned)u);
-            P.lvl[b][v] = d + 1;
+            if (layer_stores_level(P, d + 1)) P.lvl[b][v] = d + 1;
         } else if (*pp > (unsigned)u) {
             atomicMin(pp, (unsigned)u);
         }
@@ -126,9 +143,9 @@ static __device__ __forceinline__ void td_discover(const BParams &P, unsigned lo
 static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gwave, long long nwaves)
 {
     const int lane = __lane_id();
-    const unsigned long long *front = P.fm + (long long)(d % 3) * P.n;
+    const unsigned long long *front = fmask(P, d);
     const unsigned long long *ufront = P.ubm + (long long)(d % 3) * P.W;
-    unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
+    unsigned long long *next = fmask(P, d + 1);
     unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
     const long long CH = 1ll << P.hub_log2;
     for (long long idx = gwave; idx < P.n_hseg; idx += nwaves) {
@@ -166,7 +183,7 @@ static __device__ void push_bottom_up_hubs(const BParams &P, int d, long long gw
                     const int bb = __ffsll((long long)newb) - 1;
                     newb &= newb - 1;
                     atomicMin((unsigned *)&P.par[bb][v], (unsigned)u);
-                    P.lvl[bb][v] = d + 1;
+                    if (layer_stores_level(P, d + 1)) P.lvl[bb][v] = d + 1;
                 }
                 const unsigned long long all = wave_or_u64(f);
                 rem &= ~all;
@@ -245,8 +262,8 @@ static __device__ bool batch_push(const BParams &Pin, int parity, int d_hint, lo
     }
 
     const int lane = __lane_id();
-    const unsigned long long *front = P.fm + (long long)(d % 3) * P.n;
-    unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
+    const unsigned long long *front = fmask(P, d);
+    unsigned long long *next = fmask(P, d + 1);
     const unsigned long long *ufront = P.ubm + (long long)(d % 3) * P.W;
     unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
     const int G = P.wpg_td;
@@ -489,7 +506,7 @@ static __device__ void pull_bottom_up(const BParams &P, int d, const unsigned lo
                     all &= all - 1;
                     if ((mine >> b) & 1ull) {
                         P.par[b][v] = P.col[s + spos[b * 64 + lane]];
-                        P.lvl[b][v] = d + 1;
+                        if (layer_stores_level(P, d + 1)) P.lvl[b][v] = d + 1;
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -527,9 +544,11 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
     const long long m_u = view->S.m_u - view->c[3];
     const int cur = bdecide(P, view->S.dir_prev, view->c[1], view->c[2], m_u);
     const int lane = __lane_id();
-    const unsigned long long *front = P.fm + (long long)(d % 3) * P.n;
-    unsigned long long *next = P.fm + (long long)((d + 1) % 3) * P.n;
-    unsigned long long *spare = P.fm + (long long)((d + 2) % 3) * P.n;
+    const unsigned long long *front = fmask(P, d);
+    unsigned long long *next = fmask(P, d + 1);
+    // F_{d-1}'s masks are cleared for reuse only in the rotating slots; a
+    // kept slot waits for the level pass
+    unsigned long long *spare = d - 1 >= P.hist ? fmask(P, d - 1) : nullptr;
     unsigned long long *unext = P.ubm + (long long)((d + 1) % 3) * P.W;
     unsigned long long *uspare = P.ubm + (long long)((d + 2) % 3) * P.W;
     unsigned long long cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -538,7 +557,8 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
     else
         pull_bottom_up<STAGED>(P, d, front, P.ubm + (long long)(d % 3) * P.W, next, unext, gwave, nwaves, cnt,
                                spos);
-    // F_{d-1}: its masks are nonzero exactly at the vertices its bitmap marks
+    // F_{d-1}: its masks are nonzero exactly at the vertices its bitmap marks;
+    // the bitmap itself always rotates
     for (long long base = gwave * 64; base < P.W; base += nwaves * 64) {
         const long long myw = base + lane;
         const unsigned long long sw = myw < P.W ? uspare[myw] : 0ull;
@@ -547,7 +567,7 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
             const int k = __ffsll((long long)todo) - 1;
             todo &= todo - 1;
             const unsigned long long bits = bcast_u64(sw, k);
-            if ((bits >> lane) & 1ull) spare[((base + k) << 6) + lane] = 0ull;
+            if (spare && ((bits >> lane) & 1ull)) spare[((base + k) << 6) + lane] = 0ull;
         }
         if (sw) uspare[myw] = 0ull;
     }
@@ -595,42 +615,39 @@ static __device__ void batch_pull(const BParams &Pin, int parity, int d_hint, lo
 }
 
 // ---------------------------------------------------------------------------
-// Grid (x, k + 1): row y < k fills lane y's outputs with -1; row k clears
-// the masks and bitmaps, stores the output table and resets the control block.
+// Grid (x, k + 1): row y < k fills lane y's parents with -1 (the start of
+// their atomic minima; the levels are all stored by the level pass or the
+// layers); row k clears the rotating masks and bitmaps, stores the output
+// table and resets the control block.  The kept slots are already clear:
+// a new workspace starts zeroed, and every level pass clears what it read.
 __global__ void __launch_bounds__(kBlock) bfs_batch_init_kernel(BParams P, LanePtrs out)
 {
     const long long gt = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nt = (long long)gridDim.x * kBlock;
     const int y = blockIdx.y;
     if (y < P.k) {
-        int *lv = out.level[y];
         int *pa = out.parent[y];
-        const bool vec = ((((unsigned long long)lv) | ((unsigned long long)pa)) & 15ull) == 0;
+        const bool vec = (((unsigned long long)pa) & 15ull) == 0;
         const long long n4 = vec ? (P.n >> 2) : 0;
-        // non-temporal 16-byte stores: the 8·k·n bytes of -1 are not read
-        // again by this kernel, and keeping them out of L2 left more of it to
-        // the layers (whole batch 0.6% faster at SCALE 22, though this kernel
-        // itself runs a little longer)
+        // non-temporal 16-byte stores: the 4·k·n bytes of -1 are not read
+        // again by this kernel, and keeping them out of L2 leaves more of it
+        // to the layers
         typedef int v4i __attribute__((ext_vector_type(4)));
         const v4i m1 = {-1, -1, -1, -1};
-        for (long long i = gt; i < n4; i += nt) {
-            __builtin_nontemporal_store(m1, (v4i *)lv + i);
-            __builtin_nontemporal_store(m1, (v4i *)pa + i);
-        }
-        for (long long i = (n4 << 2) + gt; i < P.n; i += nt) {
-            lv[i] = -1;
-            pa[i] = -1;
-        }
+        for (long long i = gt; i < n4; i += nt) __builtin_nontemporal_store(m1, (v4i *)pa + i);
+        for (long long i = (n4 << 2) + gt; i < P.n; i += nt) pa[i] = -1;
         return;
     }
     for (long long v = gt; v < P.n; v += nt) {
         // vertices without edges count as visited in every lane: they are
         // never reached (a root among them is seeded separately)
         P.vis[v] = test_bit(P.iso, (int)v) ? P.active : 0ull;
-        // every layer clears only what it set, so all three buffers start empty
-        P.fm[v] = 0ull;
-        P.fm[P.n + v] = 0ull;
-        P.fm[2 * P.n + v] = 0ull;
+        // every layer clears only what it set, so the three rotating slots
+        // start empty
+        unsigned long long *rot = P.fm + (long long)P.hist * P.n;
+        rot[v] = 0ull;
+        rot[P.n + v] = 0ull;
+        rot[2 * P.n + v] = 0ull;
     }
     for (long long w = gt; w < P.W; w += nt) {
         P.ubm[w] = 0ull;
@@ -684,13 +701,13 @@ __global__ void __launch_bounds__(64) bfs_batch_seed_kernel(BParams P, RootSet R
     }
     unsigned long long c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
     if (on) {
-        P.lvl[lane][r] = 0;
+        if (layer_stores_level(P, 0)) P.lvl[lane][r] = 0;
         P.par[lane][r] = r;
         c5 = (unsigned long long)P.deg[r];
     }
     if (first) {
         const unsigned long long vm = test_bit(P.iso, r) ? P.active : 0ull;
-        P.fm[r] = mask;
+        fmask(P, 0)[r] = mask;
         P.vis[r] = vm | mask;
         atomicOr(&P.ubm[r >> 6], 1ull << (r & 63));
         const int dg = P.deg[r];
@@ -758,6 +775,61 @@ __global__ void __launch_bounds__(kFinishBlock) bfs_batch_finish_kernel(BParams 
     if (threadIdx.x == 0) record_failure(P.ctrl);
 }
 
+// Level pass, after the finisher: lane b's level of v for every level below
+// P.hist, read from the kept masks (bit b of v's mask in F_d: root b reached
+// v at level d), and -1 where root b never reached v; levels from P.hist on
+// were stored by their layers and are left alone.  One wavefront per bitmap
+// word, lane i on vertex 64w + i, so each store of root b's levels covers 256
+// contiguous bytes.  The per-lane level comes from four bit-slices of the
+// kept masks (slice j: the lanes whose level has bit j set).  The kept masks
+// read are cleared for the next batch: those of the levels the traversal
+// reached, or all of them after a failed traversal.
+__global__ void __launch_bounds__(kBlock) bfs_batch_levels_kernel(BParams P)
+{
+    const int lane = __lane_id();
+    const long long gwave = (long long)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const long long nwaves = (long long)gridDim.x * kWavesPerBlock;
+    const BCtrl *C = P.ctrl;
+    const bool ok = C->done == 1 && C->status == 0;
+    const int D = ok ? min(P.hist, C->nlayers) : P.hist;
+    for (long long w = gwave; w < P.W; w += nwaves) {
+        const long long v = (w << 6) + lane;
+        const bool in = v < P.n;
+        unsigned long long sl[4] = {0ull, 0ull, 0ull, 0ull};
+        unsigned long long kept = 0;          // lanes whose level of v is below P.hist
+#pragma unroll
+        for (int d = 0; d < kBatchHist; ++d) {
+            if (d < D && in) {
+                unsigned long long *slot = P.fm + (long long)d * P.n;
+                const unsigned long long h = slot[v];
+                if (h) {
+                    kept |= h;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if ((d >> j) & 1) sl[j] |= h;
+                    slot[v] = 0ull;
+                }
+            }
+        }
+        // the lanes that reached v: those that visited it, except that a
+        // vertex without edges counts as visited in every lane from the start
+        // and is reached only as a root (level 0)
+        unsigned long long reached = 0;
+        if (in) reached = test_bit(P.iso, (int)v) ? kept : P.vis[v];
+        // stored here: the kept levels and -1 for the lanes that never reached v
+        const unsigned long long mine = in ? (kept | ~reached) : 0ull;
+        if (!__ballot(mine != 0)) continue;
+        for (int b = 0; b < P.k; ++b) {
+            if (!((mine >> b) & 1ull)) continue;
+            int lev = -1;
+            if ((kept >> b) & 1ull)
+                lev = (int)((sl[0] >> b) & 1ull) | (int)(((sl[1] >> b) & 1ull) << 1) |
+                      (int)(((sl[2] >> b) & 1ull) << 2) | (int)(((sl[3] >> b) & 1ull) << 3);
+            P.lvl[b][v] = lev;
+        }
+    }
+}
+
 hipError_t launch_batch_init(const BParams &p, const LanePtrs &out, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(bfs_batch_init_kernel, dim3(grid, p.k + 1), dim3(kBlock), 0, s, p, out);
@@ -788,6 +860,12 @@ hipError_t launch_batch_finish(const BParams &p, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_batch_levels(const BParams &p, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(bfs_batch_levels_kernel, dim3(grid), dim3(kBlock), 0, s, p);
+    return hipGetLastError();
+}
+
 void *kernel_ptr_batch(int which)
 {
     switch (which) {
@@ -795,6 +873,7 @@ void *kernel_ptr_batch(int which)
     case BK_SEED: return (void *)bfs_batch_seed_kernel;
     case BK_PUSH: return (void *)bfs_batch_push_kernel;
     case BK_PULL: return (void *)bfs_batch_pull_kernel;
+    case BK_LEVELS: return (void *)bfs_batch_levels_kernel;
     default: return (void *)bfs_batch_finish_kernel;
     }
 }

@@ -284,7 +284,10 @@ struct BParams {
     int rule;
     unsigned long long active;           // bit b set for b < k
     unsigned long long *vis;             // [n] lanes that reached v in a finished layer
-    unsigned long long *fm;              // [3n] rotating lane masks: frontier / next / spare
+    // [(hist + 3) n] lane masks of the layers' frontiers: F_d in slot d for
+    // d < hist (kept for the level pass, which clears them), later layers in
+    // the three slots after those, rotating (frontier / next / spare)
+    unsigned long long *fm;
     unsigned long long *ubm;             // [3W] rotating bitmaps: vertex has a nonzero mask
     int *const *lvl;                     // device table [kLanes]: lane b's level array
     int *const *par;                     // device table [kLanes]: lane b's parent array
@@ -296,7 +299,7 @@ struct BParams {
     int async_run;                       // enqueued asynchronously
     long long alpha, beta;
     int fail_injected;                   // test hook: report this batch as failed
-    int pad;
+    int hist;                            // levels below this come from the kept masks (level pass)
 };
 
 // The init kernel copies `out` into the device tables p.lvl / p.par.
@@ -305,9 +308,15 @@ hipError_t launch_batch_seed(const BParams &p, const RootSet &roots, hipStream_t
 hipError_t launch_batch_push(const BParams &p, int layer, int grid, hipStream_t s);
 hipError_t launch_batch_pull(const BParams &p, int layer, int grid, hipStream_t s);   // blocks of kPullWaves waves
 hipError_t launch_batch_finish(const BParams &p, hipStream_t s);
+hipError_t launch_batch_levels(const BParams &p, int grid, hipStream_t s);
 int batch_blocks_per_cu();
 int batch_pull_blocks_per_cu();
 constexpr int kPullWaves = 4;             // wavefronts per block of the batched pull kernel
+// Layers whose frontier masks a batch keeps, so that their levels are stored
+// once, after the traversal, instead of by the layers (levels below 16:
+// four bit-slices).
+constexpr int kBatchHist = 12;
+static_assert(kBatchHist >= 1 && kBatchHist <= 16, "kept layers: level 0 always, four bit-slices");
 
 // Launchers (defined in bfs_kernels.hip).
 hipError_t launch_init(const Params &p, int grid, hipStream_t s);
@@ -339,7 +348,7 @@ void *kernel_ptr_bin_scan();
 void *kernel_ptr_bin_scatter();
 void *kernel_ptr_bin_reduce();
 // The batched kernels, for graph nodes (arguments as their launchers pass them).
-enum { BK_INIT, BK_SEED, BK_PUSH, BK_PULL, BK_FINISH };
+enum { BK_INIT, BK_SEED, BK_PUSH, BK_PULL, BK_FINISH, BK_LEVELS };
 void *kernel_ptr_batch(int which);
 constexpr int kReduceBlockThreads = 512;   // threads of a binned reduce block
 int layer_blocks_per_cu(bool wide);

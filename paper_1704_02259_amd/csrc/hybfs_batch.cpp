@@ -27,7 +27,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t batch_workspace_bytes(const Graph *g)
 {
     const long long n = g->n, W = g->W;
-    return align256((size_t)n * 8) + align256((size_t)n * 8 * 3) + align256((size_t)W * 8 * 3) +
+    return align256((size_t)n * 8) + align256((size_t)n * 8 * (kBatchHist + 3)) + align256((size_t)W * 8 * 3) +
            align256((size_t)std::max<long long>(g->n_hseg, 1) * 8) + align256(sizeof(BCtrl)) +
            align256((size_t)kTraceCap * sizeof(LayerRec)) + align256(2 * kLanes * sizeof(int *));
 }
@@ -57,14 +57,16 @@ int get_batch_workspace(Graph *g, void *stream, BatchWorkspace **out)
     char *b = (char *)w->dbuf;
     size_t o = 0;
     w->vis = (unsigned long long *)(b + o);  o += align256((size_t)n * 8);
-    w->fm = (unsigned long long *)(b + o);   o += align256((size_t)n * 8 * 3);
+    w->fm = (unsigned long long *)(b + o);   o += align256((size_t)n * 8 * (kBatchHist + 3));
     w->ubm = (unsigned long long *)(b + o);  o += align256((size_t)W * 8 * 3);
     w->sfound = (unsigned long long *)(b + o);  o += align256((size_t)std::max<long long>(g->n_hseg, 1) * 8);
     w->ctrl = (BCtrl *)(b + o);              o += align256(sizeof(BCtrl));
     w->trace = (LayerRec *)(b + o);          o += align256((size_t)kTraceCap * sizeof(LayerRec));
     w->tab = (int **)(b + o);
-    // used on `stream` only: a clear ordered on it suffices
-    if ((e = launch_zero(w->ctrl, align256(sizeof(BCtrl)), (hipStream_t)stream)) != hipSuccess)
+    // used on `stream` only: a clear ordered on it suffices.  The kept mask
+    // slots start clear here; afterwards each level pass clears what it read.
+    if ((e = launch_zero(w->ctrl, align256(sizeof(BCtrl)), (hipStream_t)stream)) != hipSuccess ||
+        (e = launch_zero(w->fm, align256((size_t)n * 8 * kBatchHist), (hipStream_t)stream)) != hipSuccess)
         return hip_fail(e, "workspace init");
     *out = w.get();
     g->bws[stream] = std::move(w);
@@ -106,6 +108,7 @@ static void fill_batch_params(const Graph *g, const BatchWorkspace *w, const bfs
     P->alpha = opt.alpha;
     P->beta = opt.beta;
     P->async_run = opt.async;
+    P->hist = kBatchHist;
 }
 
 static void fill_roots(const Graph *g, const int32_t *roots, int k, RootSet *R, BParams *P)
@@ -116,7 +119,8 @@ static void fill_roots(const Graph *g, const int32_t *roots, int k, RootSet *R, 
     }
 }
 
-// [init, seed, L x (push, pull), finisher] for one group of at most 64 roots.
+// [init, seed, L x (push, pull), finisher, level pass] for one group of at
+// most 64 roots.
 int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int32_t *roots, int k,
                   const LanePtrs &out, hipStream_t s, bool profile, int *layers_enqueued)
 {
@@ -145,6 +149,7 @@ int enqueue_batch(Graph *g, BatchWorkspace *w, const bfs_options &opt, const int
         if (profile && (e = hipEventRecord(w->layer_ev[2 * i + 1], s)) != hipSuccess) return hip_fail(e, "event");
     }
     if ((e = launch_batch_finish(P, s)) != hipSuccess) return hip_fail(e, "batch finisher launch");
+    if ((e = launch_batch_levels(P, grid, s)) != hipSuccess) return hip_fail(e, "batch level pass launch");
     *layers_enqueued = L;
     return BFS_OK;
 }
@@ -205,8 +210,9 @@ int enqueue_batch_graph(Graph *g, BatchWorkspace *w, const bfs_options &opt, con
                 (e = add(BK_PULL, dim3(pgrid), dim3(kPullWaves * 64), args, nullptr)) != hipSuccess)
                 return fail(e, "graph batch layer nodes");
         }
-        if ((e = add(BK_FINISH, dim3(1), dim3(kFinishBlock), fin_args, nullptr)) != hipSuccess)
-            return fail(e, "graph batch finisher node");
+        if ((e = add(BK_FINISH, dim3(1), dim3(kFinishBlock), fin_args, nullptr)) != hipSuccess ||
+            (e = add(BK_LEVELS, dim3(grid), dim3(kBlock), fin_args, nullptr)) != hipSuccess)
+            return fail(e, "graph batch finisher nodes");
         if ((e = hipGraphInstantiate(&Q.exec, Q.graph, nullptr, nullptr, 0)) != hipSuccess)
             return fail(e, "graph instantiate");
         it = w->replays.emplace(key, Q).first;

@@ -86,7 +86,7 @@ struct BatchWorkspace {
     void *dbuf = nullptr;
     size_t bytes = 0;
     unsigned long long *vis = nullptr;   // [n]
-    unsigned long long *fm = nullptr;    // [3n]
+    unsigned long long *fm = nullptr;    // [(kBatchHist + 3) n]: kept, then rotating
     unsigned long long *ubm = nullptr;   // [3W]
     unsigned long long *sfound = nullptr;  // [n_hseg] lanes each hub-row segment found
     BCtrl *ctrl = nullptr;

@@ -249,6 +249,73 @@ def test_batch_edge_case_graphs(torch, hyb, case):
     G.close()
 
 
+def _kept_layers():
+    """kBatchHist, the layers whose frontier masks a batch keeps, as the
+    kernels' header defines it."""
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "paper_1704_02259_amd", "csrc", "bfs_device.h")) as f:
+        m = re.search(r"constexpr int kBatchHist = (\d+);", f.read())
+    assert m, "kBatchHist not found"
+    return int(m.group(1))
+
+
+def test_batch_depths_around_kept_layers(torch, hyb):
+    """The levels of a batch's first layers are stored after the traversal
+    from the kept frontier masks, the deeper ones by their layers (and the
+    finisher): paths whose depths end just below, at and above that boundary,
+    with lanes of different depths in one batch, several launch depths, graph
+    replays, and deep and shallow batches in turn on one workspace (the kept
+    masks must be clear again for the next batch)."""
+    H = _kept_layers()
+    for n in (H - 1, H, H + 1, H + 2, 3 * H + 5):
+        g = inputs.path_graph(n)
+        G = hyb.Graph.from_csr(g)
+        sets = [[0], [n - 1, 0, n // 2], [n // 2], [0, n - 1] * 3, [n // 3, 1]]
+        for i, roots in enumerate(sets):
+            roots = np.array(roots, dtype=np.int32)
+            for kw in ({}, {"layers_per_launch": 1}, {"layers_per_launch": H}, {"layers_per_launch": H + 1},
+                       {"graph_launch": 1}, {"graph_launch": 1, "layers_per_launch": 2}):
+                _say("path", n, "set", i, kw)
+                lv, pa, st = _gpu_batch(torch, G, roots, **kw)
+                _check_rows(g, f"path{n}", roots, lv, pa)
+                _check_stats(g, f"path{n}", roots, st)
+        G.close()
+
+
+def test_batch_after_a_failed_batch(torch, hyb):
+    """A batch that fails a device-side check (forced from the host with the
+    library's test hook: the finisher reports the traversal as failed while
+    every kernel runs normally) is reported, and the next batches on the same
+    workspace are exact: the level pass clears every kept mask after a
+    failure."""
+    import os
+    from paper_1704_02259_amd import hybfs
+    g = inputs.kronecker(12)
+    roots = [int(r) for r in inputs.pick_roots(g, 5, 2212)]
+    old = os.environ.pop("HYBFS_TEST_FAIL_ROOT", None)
+    try:
+        os.environ["HYBFS_TEST_FAIL_ROOT"] = str(roots[0])
+        G = hyb.Graph.from_csr(g)
+    finally:
+        os.environ.pop("HYBFS_TEST_FAIL_ROOT", None)
+        if old is not None:
+            os.environ["HYBFS_TEST_FAIL_ROOT"] = old
+    for kw in ({}, {"graph_launch": 1}):
+        _say("failing batch", kw)
+        with pytest.raises(hybfs.HybfsError) as ei:
+            _gpu_batch(torch, G, np.array(roots, dtype=np.int32), **kw)
+        assert ei.value.code == hybfs.BFS_E_DEVICE
+        for sub in (roots[1:], roots[2:4]):
+            sub = np.array(sub, dtype=np.int32)
+            _say("batch after the failure", kw, list(sub))
+            lv, pa, st = _gpu_batch(torch, G, sub, **kw)
+            _check_rows(g, "kron12", sub, lv, pa)
+            _check_stats(g, "kron12", sub, st)
+    G.close()
+
+
 def test_batch_unsorted_rows(torch, hyb):
     base = inputs.kronecker(10)
     rng = np.random.default_rng(4)
