@@ -795,27 +795,28 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_levels_kernel(BParams P)
     for (long long w = gwave; w < P.W; w += nwaves) {
         const long long v = (w << 6) + lane;
         const bool in = v < P.n;
+        // all kept masks of v in flight together
+        unsigned long long h[kBatchHist];
+#pragma unroll
+        for (int d = 0; d < kBatchHist; ++d) h[d] = (d < D && in) ? P.fm[(long long)d * P.n + v] : 0ull;
+        const unsigned long long vis = in ? P.vis[v] : 0ull;
+        const bool iso = in && test_bit(P.iso, (int)v);
         unsigned long long sl[4] = {0ull, 0ull, 0ull, 0ull};
         unsigned long long kept = 0;          // lanes whose level of v is below P.hist
 #pragma unroll
         for (int d = 0; d < kBatchHist; ++d) {
-            if (d < D && in) {
-                unsigned long long *slot = P.fm + (long long)d * P.n;
-                const unsigned long long h = slot[v];
-                if (h) {
-                    kept |= h;
+            kept |= h[d];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if ((d >> j) & 1) sl[j] |= h;
-                    slot[v] = 0ull;
-                }
-            }
+            for (int j = 0; j < 4; ++j)
+                if ((d >> j) & 1) sl[j] |= h[d];
         }
+#pragma unroll
+        for (int d = 0; d < kBatchHist; ++d)
+            if (h[d]) P.fm[(long long)d * P.n + v] = 0ull;
         // the lanes that reached v: those that visited it, except that a
         // vertex without edges counts as visited in every lane from the start
         // and is reached only as a root (level 0)
-        unsigned long long reached = 0;
-        if (in) reached = test_bit(P.iso, (int)v) ? kept : P.vis[v];
+        const unsigned long long reached = iso ? kept : vis;
         // stored here: the kept levels and -1 for the lanes that never reached v
         const unsigned long long mine = in ? (kept | ~reached) : 0ull;
         if (!__ballot(mine != 0)) continue;
@@ -825,7 +826,7 @@ __global__ void __launch_bounds__(kBlock) bfs_batch_levels_kernel(BParams P)
             if ((kept >> b) & 1ull)
                 lev = (int)((sl[0] >> b) & 1ull) | (int)(((sl[1] >> b) & 1ull) << 1) |
                       (int)(((sl[2] >> b) & 1ull) << 2) | (int)(((sl[3] >> b) & 1ull) << 3);
-            P.lvl[b][v] = lev;
+            __builtin_nontemporal_store(lev, &P.lvl[b][v]);
         }
     }
 }
