@@ -462,7 +462,7 @@ def join_batch_counters(map_path, csv_paths, fetch_factor=2.0, write_factor=1.0)
     """Per-dispatch durations (a rocprofv3 --kernel-trace CSV) and counters
     (--pmc CSVs) of the last plain batch batch_profile ran, by launch order:
     a batch starts at its init kernel, then the seed kernel, then one push and
-    one pull kernel per enqueued layer, then the finisher."""
+    one pull kernel per enqueued layer, then the finisher and the level pass."""
     import csv
     with open(map_path) as f:
         bm = json.load(f)
